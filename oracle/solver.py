@@ -1,0 +1,230 @@
+"""Algorithm 1 (algFFT) of the paper, written out step by step in FP64.
+
+For every load increment: update u* (Alg. line 3) and its discrete gradient
+(line 4; D* = 0, no applied tractions), predict u^f from the previous
+increment (line 5), then iterate:
+
+  * strain at the integration points, grad_d u = grad_d u^f + grad_d u*  (l.7)
+  * stress from the behaviour law                                         (l.8)
+  * D = div_d P + D*                                                      (l.9)
+  * equilibrium error, Eq. equilibrium_condition                          (l.10)
+  * stop if below the tolerance                                           (l.11-16)
+  * p = div_d(R0 : grad_d u^f) - D                                        (l.17)
+  * Anderson acceleration on p                                            (l.18)
+  * DTs of the accelerated p, Green operator, inverse DTs -> u^f          (l.19-21)
+
+Readings where the paper is silent or garbled (listed in the design doc):
+  * error  = h sqrt( sum_kept |D|^2 / sum_ip w_ip |sigma|_F^2 ), w_ip = 1/n_ppv
+    (squared L2 norms; the printed ratio of norms is not dimensionless);
+  * Anderson (Sec. 2.3: "every 2 or 3 iterations ... previous 4 couples"):
+    type-II Anderson on the Green input x with g_m = p_m, f_m = g_m - x_{m-1},
+    the last ``aa_depth`` pairs, applied when m >= 2 and m % aa_period == 0,
+    weights minimising |sum a_j f_j|^2 with sum a_j = 1 (normal equations,
+    ridge 1e-14 trace, skipped if the Cholesky pivots differ by more than a
+    factor 1e12 in square), history cleared at every increment; before the
+    first iteration x_{-1} = L0(u^f_0) so that u^f_0 = Green(x_{-1});
+  * R0 = B0 (or 2 mu0 when lambda0 = 0) acts on the non-symmetric gradient;
+  * mixed control (Sec. 3.2, NMBC1 loading): after each iteration the
+    stress-controlled Voigt components of sym(G) move by
+    C0|_SS^{-1} (Sigma*_S - <sigma>_S) with the isotropic lambda0, mu0;
+    an increment also requires max_S |<sigma>_S - Sigma*_S| <= tol |<sigma>|.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import dt as _dt
+from . import fd as _fd
+from . import green as _green
+from .laws import MaterialSet
+
+VOIGT = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+
+
+class Plan:
+    def __init__(self, prob):
+        self.n = tuple(int(v) for v in prob.n)
+        self.h = float(prob.h)
+        self.scheme = int(prob.scheme)
+        self.nppv = _fd.n_ppv(self.scheme)
+        self.lam0 = float(prob.lambda0)
+        self.mu0 = float(prob.mu0)
+        self.green = int(prob.green)
+        bc = np.asarray(prob.bc)
+        self.exts = [[(_dt.ext_of_bc(bc[q, i, 0]), _dt.ext_of_bc(bc[q, i, 1])) for i in range(3)]
+                     for q in range(3)]
+        self.kinds = [[_dt.pair_kind(*self.exts[q][i]) for i in range(3)] for q in range(3)]
+        self.kept = [_fd.kept_mask(self.exts[q], self.n) for q in range(3)]
+        n1, n2, n3 = self.n
+        j = [np.arange(self.n[i] + 1) * self.h for i in range(3)]
+        self.X = np.meshgrid(j[0], j[1], j[2], indexing="ij")
+
+    # -- operators -----------------------------------------------------------
+    def ustar(self, c, G, H):
+        X = self.X
+        u = np.zeros((3,) + X[0].shape)
+        for q in range(3):
+            u[q] = c[q]
+            for l in range(3):
+                u[q] += G[q, l] * X[l]
+                for m in range(3):
+                    u[q] += 0.5 * H[q, l, m] * X[l] * X[m]
+        return u
+
+    def grad(self, u):
+        return _fd.gradient(u, self.scheme, self.h)
+
+    def div(self, S):
+        return _fd.divergence(S, self.exts, self.scheme, self.h)
+
+    def L0(self, u):
+        """div_d(R0 : grad_d u) with R0 = B0 (2 mu0 grad u + lambda0 grad u . I)."""
+        g = self.grad(u)
+        lam = self.lam0 if self.green == 0 else 0.0
+        tau0 = g * (2.0 * self.mu0 + lam * np.eye(3))    # factor on entry (l, q)
+        return self.div(tau0)
+
+    def green_apply(self, x):
+        u = np.zeros_like(x)
+        for q in range(3):
+            xh = _dt.forward_3d(x[q], self.kinds[q])
+            uh = _green.apply(xh, self.kinds[q], self.n, q, self.scheme, self.h,
+                              self.lam0, self.mu0, self.green)
+            u[q] = _dt.inverse_3d(uh, self.kinds[q], self.n)
+            _fd.zero_dismissed(u[q], self.exts[q])
+        return u
+
+    def dot_kept(self, a, b):
+        return float(sum(np.sum(a[q][self.kept[q]] * b[q][self.kept[q]]) for q in range(3)))
+
+
+def anderson_weights(F: np.ndarray):
+    k = F.shape[0]
+    Fr = F + 1e-14 * np.trace(F) * np.eye(k)
+    try:
+        L = np.linalg.cholesky(Fr)
+    except np.linalg.LinAlgError:
+        return None
+    d = np.diag(L) ** 2
+    if d.min() <= 1e-12 * d.max():
+        return None
+    y = np.linalg.solve(Fr, np.ones(k))
+    return y / y.sum()
+
+
+def c0_voigt(lam0, mu0):
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam0
+    for a in range(3):
+        C[a, a] += 2.0 * mu0
+    for a in range(3, 6):
+        C[a, a] = 2.0 * mu0
+    return C
+
+
+def solve(prob, callback=None):
+    """Run Algorithm 1 on a ``workloads.Problem``.  Returns a dict with the
+    outputs in the library layout (x fastest): u (3, n3+1, n2+1, n1+1),
+    eps and sig (6, n_ppv, n3, n2, n1) in Voigt order, per-step macroscopic
+    stress, iteration counts, convergence flags and the iteration log."""
+    pl = Plan(prob)
+    n = pl.n
+    mats = MaterialSet(prob.materials, np.asarray(prob.mat_id).transpose(2, 1, 0))
+    state = mats.init_state(pl.nppv, n)
+    uf = np.zeros((3, n[0] + 1, n[1] + 1, n[2] + 1))
+    nvox = n[0] * n[1] * n[2]
+    log, macro, iters, conv, Gs = [], [], [], [], []
+    C0 = c0_voigt(pl.lam0, pl.mu0)
+    for t, step in enumerate(prob.steps):
+        G = np.array(step.G, dtype=np.float64).copy()
+        if t > 0 and np.any(step.mixed_mask) and len(Gs):
+            Gprev = Gs[-1]
+            for a in np.nonzero(step.mixed_mask)[0]:
+                i, j = VOIGT[a]
+                G[i, j] = Gprev[i, j]
+                G[j, i] = Gprev[j, i]
+        S_idx = np.nonzero(step.mixed_mask)[0]
+        hist = []
+        x_prev = pl.L0(uf)
+        converged = False
+        m = 0
+        while True:
+            us = pl.ustar(step.c, G, step.H)
+            gu = pl.grad(uf) + pl.grad(us)
+            eps = 0.5 * (gu + np.swapaxes(gu, -1, -2))
+            sig, trial = mats.stress(eps, state, step.dt)
+            Dv = pl.div(sig)
+            sD = pl.dot_kept(Dv, Dv)
+            sS = float(np.sum(sig * sig)) / pl.nppv
+            if sS > 0:
+                err = pl.h * np.sqrt(sD / sS)
+            else:
+                err = 0.0 if sD == 0 else np.inf
+            ms = sig.mean(axis=(0, 1, 2, 3))
+            mvo = np.array([ms[i, j] for (i, j) in VOIGT])
+            mixed_ok = True
+            if S_idx.size:
+                r = step.mixed_target[S_idx] - mvo[S_idx]
+                mixed_ok = np.max(np.abs(r)) <= prob.tol * np.linalg.norm(ms)
+            log.append({"step": t, "iter": m, "err": err, "macro_sigma": mvo.copy()})
+            if callback is not None:
+                callback(t, m, err)
+            if err < prob.tol and mixed_ok:
+                converged = True
+                break
+            if m >= prob.max_iter:
+                break
+            if S_idx.size:
+                dE = np.linalg.solve(C0[np.ix_(S_idx, S_idx)], r)
+                for a, v in zip(S_idx, dE):
+                    i, j = VOIGT[a]
+                    if i == j:
+                        G[i, i] += v
+                    else:
+                        G[i, j] += v
+                        G[j, i] += v
+            p = pl.L0(uf) - Dv
+            g = p
+            f = g - x_prev
+            hist.append((g, f))
+            hist = hist[-prob.aa_depth:]
+            aa = False
+            x = g
+            if m >= 2 and m % prob.aa_period == 0 and len(hist) >= 2:
+                k = len(hist)
+                F = np.array([[pl.dot_kept(hist[a][1], hist[b][1]) for b in range(k)]
+                              for a in range(k)])
+                al = anderson_weights(F)
+                if al is not None:
+                    x = sum(al[a] * hist[a][0] for a in range(k))
+                    aa = True
+            log[-1]["aa"] = aa
+            uf = pl.green_apply(x)
+            x_prev = x
+            m += 1
+        state = trial
+        Gs.append(G.copy())
+        macro.append(mvo)
+        iters.append(m)
+        conv.append(converged)
+    us = pl.ustar(prob.steps[-1].c, Gs[-1], prob.steps[-1].H)
+    u = uf + us
+
+    def vox_out(T):
+        out = np.empty((6, pl.nppv, n[2], n[1], n[0]))
+        for a, (i, j) in enumerate(VOIGT):
+            out[a] = T[..., i, j].transpose(0, 3, 2, 1)
+        return out
+
+    return {
+        "u": u.transpose(0, 3, 2, 1).copy(),
+        "uf": uf.transpose(0, 3, 2, 1).copy(),
+        "eps": vox_out(eps),
+        "sig": vox_out(sig),
+        "macro_sigma": np.array(macro),
+        "iters": iters,
+        "converged": conv,
+        "G": np.array(Gs),
+        "log": log,
+        "nvox": nvox,
+    }

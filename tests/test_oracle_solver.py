@@ -1,0 +1,215 @@
+"""Pins of the oracle fixed point (Algorithm 1).
+
+P7: on tiny grids the converged fields equal a direct least-squares solve of
+    the discrete finite-difference equilibrium D(u^f + u*) = 0 on the kept
+    nodes, assembled column by column (random two-phase elastic problems,
+    random per-face, per-component BCs, both schemes, both Green operators).
+P8: a homogeneous body under affine-compatible BCs converges to the exact
+    affine field (the FD gradient of an affine field is exact).
+P9: a periodic two-phase laminate with layers on node planes reproduces the
+    analytic laminate strains (continuity of traction, mean strain imposed).
+P10: <sigma> does not depend on lambda0, mu0, the Green operator or the
+    Anderson settings (within the solver tolerance).
+P11: a homogeneous J2 body under uniaxial stress (u_z Dirichlet on z faces,
+    all other faces / components Neumann) follows the bilinear closed form.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dt, fd, solver
+from oracle.laws import MaterialSet
+
+
+def _residual_operator(prob):
+    pl = solver.Plan(prob)
+    mats = MaterialSet(prob.materials, np.asarray(prob.mat_id).transpose(2, 1, 0))
+    state = mats.init_state(pl.nppv, pl.n)
+    step = prob.steps[0]
+    us = pl.ustar(step.c, step.G, step.H)
+
+    def D_of(uf):
+        gu = pl.grad(uf) + pl.grad(us)
+        eps = 0.5 * (gu + np.swapaxes(gu, -1, -2))
+        sig, _ = mats.stress(eps, state, 1.0)
+        return pl.div(sig), eps, sig
+
+    return pl, D_of
+
+
+def _direct_solve(prob):
+    pl, D_of = _residual_operator(prob)
+    shape = (3,) + tuple(v + 1 for v in pl.n)
+    idx = [np.argwhere(pl.kept[q]) for q in range(3)]
+    cols = [(q, tuple(i)) for q in range(3) for i in idx[q]]
+    rows = cols
+    z = np.zeros(shape)
+    D0 = D_of(z)[0]
+    b = -np.array([D0[q][i] for q, i in rows])
+    A = np.zeros((len(rows), len(cols)))
+    for c, (q, i) in enumerate(cols):
+        e = np.zeros(shape)
+        e[q][i] = 1.0
+        for qq in range(3):
+            fd.zero_dismissed(e[qq], pl.exts[qq])
+        Dc = D_of(e)[0]
+        A[:, c] = [Dc[qq][ii] for qq, ii in rows] + b
+    x = np.linalg.lstsq(A, b, rcond=1e-12)[0]
+    uf = np.zeros(shape)
+    for (q, i), v in zip(cols, x):
+        uf[q][i] = v
+    for q in range(3):
+        fd.zero_dismissed(uf[q], pl.exts[q])
+    D, eps, sig = D_of(uf)
+    return eps, sig, np.abs(A @ x - b).max()
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+@pytest.mark.parametrize("seed", range(4))
+def test_fixed_point_equals_direct_solve(scheme, seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = (4, 3, 5) if seed % 2 else (3, 4, 4)
+    prob = W.random_small_problem(rng, n=n, scheme=scheme, tol=1e-12)
+    prob.green = seed % 2
+    eps_d, sig_d, res = _direct_solve(prob)
+    assert res < 1e-10
+    r = solver.solve(prob)
+    assert r["converged"][0]
+    sig = r["sig"]
+    ref = np.stack([sig_d[..., i, j] for (i, j) in solver.VOIGT]).transpose(0, 1, 4, 3, 2)
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(sig, ref, atol=1e-8 * scale)
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+def test_homogeneous_affine(scheme):
+    n = (6, 5, 7)
+    bc = np.full((3, 3, 2), W.N, dtype=np.int32)
+    bc[2, 2, :] = W.D
+    bc[:, 1, :] = W.P
+    lam, mu = W.iso_from_E_nu(2.0, 0.3)
+    G = np.zeros((3, 3)); G[2, 2] = 1e-3
+    prob = W.Problem(n=n, h=1.0, bc=bc, scheme=scheme, green=W.GREEN_B0, lambda0=lam,
+                     mu0=mu, materials=[W.mat_iso(lam, mu)],
+                     mat_id=np.zeros((n[2], n[1], n[0]), dtype=np.int32),
+                     steps=[W.step_affine(G)], tol=1e-12, max_iter=500)
+    r = solver.solve(prob)
+    assert r["converged"][0]
+    # y periodic with <eps_yy> = 0: plane strain in y, free contraction in x
+    nu = 0.3
+    exp = np.array([-nu / (1 - nu) * 1e-3, 0.0, 1e-3, 0, 0, 0])
+    for a in range(6):
+        np.testing.assert_allclose(r["eps"][a], exp[a], atol=1e-13)
+    np.testing.assert_allclose(r["sig"][2], 2.0 / (1 - nu ** 2) * 1e-3, rtol=1e-10)
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+def test_periodic_laminate(scheme):
+    n = (4, 3, 8)
+    k = 3                                     # voxels 0..k-1 along z are phase 1
+    ids = np.zeros((n[2], n[1], n[0]), dtype=np.int32)
+    ids[:k] = 1
+    mA = W.iso_from_E_nu(1.0, 0.3)
+    mB = W.iso_from_E_nu(7.0, 0.2)
+    E = np.array([[1e-3, 2e-4, -3e-4], [2e-4, -5e-4, 4e-4], [-3e-4, 4e-4, 8e-4]])
+    prob = W.Problem(n=n, h=1.0, bc=np.zeros((3, 3, 2), dtype=np.int32), scheme=scheme,
+                     green=W.GREEN_B0, lambda0=max(mA[0], mB[0]), mu0=max(mA[1], mB[1]),
+                     materials=[W.mat_iso(*mA), W.mat_iso(*mB)], mat_id=ids,
+                     steps=[W.step_affine(E)], tol=1e-12, max_iter=2000)
+    r = solver.solve(prob)
+    assert r["converged"][0]
+    # analytic: eps_k = E + sym(a_k x e3), f_B a_B + f_A a_A = 0, traction continuous
+    fB, fA = k / n[2], 1 - k / n[2]
+
+    def C(lam, mu):
+        d = np.eye(3)
+        return lam * np.einsum("ij,kl->ijkl", d, d) + mu * (np.einsum("ik,jl->ijkl", d, d)
+                                                             + np.einsum("il,jk->ijkl", d, d))
+    CA, CB = C(*mA), C(*mB)
+    e3 = np.array([0.0, 0.0, 1.0])
+
+    def trac(Cm, a):
+        eps = E + 0.5 * (np.outer(a, e3) + np.outer(e3, a))
+        return np.einsum("ijkl,kl->ij", Cm, eps) @ e3
+
+    # linear in aA (aB = -fA/fB aA): solve trac(CA, aA) = trac(CB, aB)
+    M = np.zeros((3, 3)); rhs = trac(CB, np.zeros(3)) - trac(CA, np.zeros(3))
+    for j in range(3):
+        a = np.zeros(3); a[j] = 1.0
+        M[:, j] = (trac(CA, a) - trac(CA, 0 * a)) - (trac(CB, -fA / fB * a) - trac(CB, 0 * a))
+    aA = np.linalg.solve(M, rhs)
+    aB = -fA / fB * aA
+    for zsl, a in ((slice(0, k), aB), (slice(k, None), aA)):
+        eps = E + 0.5 * (np.outer(a, e3) + np.outer(e3, a))
+        for c, (i, j) in enumerate(solver.VOIGT):
+            np.testing.assert_allclose(r["eps"][c][:, zsl], eps[i, j], atol=1e-12)
+
+
+def test_invariance_to_reference_medium_and_acceleration():
+    rng = np.random.default_rng(77)
+    base = W.random_small_problem(rng, n=(5, 6, 4), scheme=W.TETRA2, tol=1e-11)
+    ref = solver.solve(base)["macro_sigma"][0]
+    variants = []
+    for lam_f, mu_f, green, depth, period in ((0.5, 1.3, 0, 4, 3), (2.0, 0.8, 0, 1, 3),
+                                              (1.0, 1.0, 1, 3, 2), (1.0, 2.0, 0, 4, 2)):
+        p = W.random_small_problem(np.random.default_rng(77), n=(5, 6, 4), scheme=W.TETRA2,
+                                   tol=1e-11)
+        p.lambda0 *= lam_f; p.mu0 *= mu_f; p.green = green
+        p.aa_depth = depth; p.aa_period = period
+        variants.append(solver.solve(p)["macro_sigma"][0])
+    for v in variants:
+        np.testing.assert_allclose(v, ref, atol=1e-9 * np.abs(ref).max())
+
+
+def test_j2_uniaxial_stress_bilinear():
+    n = (3, 3, 4)
+    E, nu, sy0, H = 70.0, 0.33, 0.1, 1.0
+    lam, mu = W.iso_from_E_nu(E, nu)
+    bc = np.full((3, 3, 2), W.N, dtype=np.int32)
+    bc[2, 2, :] = W.D
+    steps = []
+    ez = np.linspace(0, 5e-3, 11)[1:]
+    for e in ez:
+        s = W.LoadStep(); s.G[2, 2] = e
+        steps.append(s)
+    prob = W.Problem(n=n, h=1.0, bc=bc, scheme=W.HEX1, green=W.GREEN_B0, lambda0=lam,
+                     mu0=mu, materials=[W.mat_j2(lam, mu, sy0, H)],
+                     mat_id=np.zeros((n[2], n[1], n[0]), dtype=np.int32), steps=steps,
+                     tol=1e-12, max_iter=800)
+    r = solver.solve(prob)
+    assert all(r["converged"])
+    ey = sy0 / E
+    Et = E * H / (E + H)
+    for t, e in enumerate(ez):
+        exact = E * e if e <= ey else sy0 + Et * (e - ey)
+        assert r["macro_sigma"][t][2] == pytest.approx(exact, rel=1e-9)
+        assert abs(r["macro_sigma"][t][0]) < 1e-9
+
+
+def test_mixed_control_uniaxial_stress_j2():
+    """C3's boundary conditions on a homogeneous J2 body: x, y periodic, z faces
+    u_z Dirichlet / u_x, u_y Neumann, <sigma_xx> = <sigma_yy> = 0 enforced by
+    the mixed update -> uniaxial stress, bilinear closed form."""
+    n = (3, 4, 4)
+    E, nu, sy0, H = 70.0, 0.33, 0.1, 1.0
+    lam, mu = W.iso_from_E_nu(E, nu)
+    bc = np.zeros((3, 3, 2), dtype=np.int32)
+    bc[0, 2, :] = W.N; bc[1, 2, :] = W.N; bc[2, 2, :] = W.D
+    steps = []
+    ez = np.linspace(0, 4e-3, 9)[1:]
+    for e in ez:
+        s = W.LoadStep(); s.G[2, 2] = e
+        s.mixed_mask = np.array([1, 1, 0, 0, 0, 0], dtype=np.int32)
+        steps.append(s)
+    prob = W.Problem(n=n, h=1.0, bc=bc, scheme=W.HEX1, green=W.GREEN_B0, lambda0=lam,
+                     mu0=mu, materials=[W.mat_j2(lam, mu, sy0, H)],
+                     mat_id=np.zeros((n[2], n[1], n[0]), dtype=np.int32), steps=steps,
+                     tol=1e-11, max_iter=800)
+    r = solver.solve(prob)
+    assert all(r["converged"])
+    ey = sy0 / E
+    Et = E * H / (E + H)
+    for t, e in enumerate(ez):
+        exact = E * e if e <= ey else sy0 + Et * (e - ey)
+        assert r["macro_sigma"][t][2] == pytest.approx(exact, rel=1e-8)
+        assert abs(r["macro_sigma"][t][0]) < 1e-10 * exact
