@@ -1,0 +1,116 @@
+// Shared device/host definitions of the MI355X solver (gfx950, HIP).
+//
+// Layout conventions (all fields live in the caller's workspace):
+//   node field, component q:   base + q*Nn,  Nn = N0*N1*N2, N = n + 1, x fastest
+//   voxel field, comp c, ip r: base + (c*nppv + r)*Nv, Nv = n0*n1*n2
+//   spectral buffers:          per component, dims change one axis per pass
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fm {
+
+// Transform kinds of Table 1, selected by the pair of extensions at the two
+// ends of an axis: P/P -> DFT, S/S -> DCT-I, A/A -> DST-I, S/A -> DCT-III,
+// A/S -> DST-III.
+enum Kind : int { K_DFT = 0, K_DCT1 = 1, K_DST1 = 2, K_DCT3 = 3, K_DST3 = 4 };
+
+enum Status : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 2, ST_IDLE = 3 };
+
+constexpr int MAX_DEPTH = 4;
+constexpr int MAX_RADICES = 12;
+constexpr int MT_STRIDE = 160;      // reals per material table entry
+constexpr int NPART_S = 8;          // reals per stress partial: sum w|s|^2, sum s_c (6), pad
+constexpr int NGRAM = 10;           // upper triangle of a 4x4 Gram matrix
+
+// Per-solve control block (device).  Written by the control kernels, read by
+// every kernel of an iteration.
+struct Ctrl {
+  int32_t m;              // index of the iterate being evaluated (per increment)
+  int32_t status;         // Status
+  int32_t aa_pending;     // Gram requested this iteration
+  int32_t aa_applied;
+  int32_t n_d;            // terms of the Green input  x = sum alpha_j D_{slot_d[j]}
+  int32_t slot_d[MAX_DEPTH];
+  int32_t n_b;            // terms of sum beta_k delta_{slot_b[k]}
+  int32_t slot_b[MAX_DEPTH];
+  int32_t slot_w;         // delta slot written by this iteration
+  int32_t win_n;          // iterates in the history window
+  int32_t win_slot[MAX_DEPTH];   // D slots of the window, oldest first
+  int32_t step;
+  int32_t log_count;
+  int32_t max_iter, depth, period;
+  int32_t mixed_mask[6];
+  int32_t pad_[3];
+  double alpha[MAX_DEPTH];
+  double beta[MAX_DEPTH];
+  double err, sumD2, sumS2;
+  double macro[6];
+  double c[3];
+  double G[9];            // G[q*3+l]
+  double H[27];           // H[(q*3+l)*3+m], symmetric in l, m
+  double mixed_target[6];
+  double dt, tol;
+  double lam0, mu0;
+};
+
+struct LogEntry {
+  double err;
+  double aa;
+  double macro[6];
+};
+
+// Per-solve descriptor (device).
+struct SolveDev {
+  int32_t n[3], N[3];
+  int64_t Nn, Nv;
+  int32_t scheme, nppv, depth, has_state;
+  int32_t kinds[3][3];    // [q][axis]
+  double h, lam0, mu0;
+  double* uf;             // 3*Nn (FP64 always)
+  void* Dring;            // depth * 3 * Nn reals
+  void* dring;            // depth * 3 * Nn reals
+  void* sig;              // 6 * nppv * Nv reals
+  const uint16_t* mat;    // Nv
+  const void* mtab;       // material table, MT_STRIDE reals per entry
+  const int32_t* mlaw;    // law per material
+  void* state;            // 7 * nppv * Nv reals (or null)
+  Ctrl* ctrl;
+  LogEntry* log;
+  double* part_s;         // ntile_s * NPART_S
+  double* part_d;         // ntile_d
+  double* part_g;         // ntile_d * NGRAM
+  int32_t ntile_s, ntile_d;
+  double* out_u;
+  double* out_eps;
+  double* out_sig;
+};
+
+// One axis pass of one component of one solve (device).
+struct PassDesc {
+  int32_t solve;
+  int32_t q;
+  int32_t kind, n, L, nrad;
+  int32_t rad[MAX_RADICES];
+  int32_t cplx_in, cplx_out, packed;
+  int32_t len_in, len_out;        // extent along the axis in input / output arrays
+  int32_t n_p0, n_p1;             // pencil grid (p0 contiguous for strided passes)
+  int32_t cols, tiles_p0;         // columns (or rows for x passes) per block
+  int32_t F;                      // FFTs per block
+  int64_t in_sa, in_s1, out_sa, out_s1;   // element strides
+  void* in;
+  void* out;
+  const void* tw;                 // L twiddles exp(-2 pi i t / L)
+  // x-pass extras: Anderson combination input / displacement update output
+  void* ring;                     // component base of D ring (fwd) or delta ring (inv)
+  int64_t ring_stride;            // reals between slots
+  double* uf;                     // component base of u^f (inv x pass)
+  // Green (fused z pass): per-axis tables of this component
+  const double* gs2[3];           // sin^2(xi/2) per spectral index
+  const double* gc2[3];           // cos^2(xi/2)
+  const uint8_t* gfl[3];          // bit0: xi = 0, bit1: xi = pi
+  int32_t scheme, green_lam;      // green_lam: 1 uses lambda0 (B0), 0 for 2mu0
+  double h, lam0, mu0;
+};
+
+}  // namespace fm

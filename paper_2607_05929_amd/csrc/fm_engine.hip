@@ -1,0 +1,971 @@
+// Host engine and C ABI of the MI355X displacement-based FFT solver.
+//
+// A plan carves every buffer of one solve out of the caller's workspace;
+// a group (one plan, a batch, or the server's active set) owns the device
+// arrays that let a single kernel launch cover the tiles of all its solves.
+// The iteration sequence (Alg. 1, lines 7-21) is ten launches; all decisions
+// (convergence, Anderson schedule and weights, mixed loading) are taken on
+// the device, so the host enqueues iterations in chunks and only reads a few
+// status words between chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fmsolve.h"
+#include "fm_pass.h"
+#include "fm_space.h"
+
+using namespace fm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return fail(FM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v, size_t a = ALIGN) { return (v + a - 1) / a * a; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Geometry of one solve
+// ---------------------------------------------------------------------------
+struct Geometry {
+  int n[3], N[3];
+  int64_t Nn, Nv;
+  int nppv, rbytes, depth;
+  int kinds[3][3];
+  int M[3][3];       // spectral extents [q][axis]
+  int cplx[3][3];    // element complex after forward pass on axis a
+  int64_t s1[3], s2[3];   // reals of stage-1 / stage-2 buffers per component
+  int L[3][3];
+  int F[3][5];       // FFTs per block per pass
+  int ntile_s, ntile_d;
+};
+
+int kind_of(int left, int right, int* out) {
+  auto ext = [](int bc) { return bc == FM_BC_PERIODIC ? 0 : (bc == FM_BC_DIRICHLET ? -1 : 1); };
+  const int a = ext(left), b = ext(right);
+  if (a == 0 || b == 0) {
+    if (a != b) return -1;
+    *out = K_DFT;
+    return 0;
+  }
+  if (a == 1 && b == 1) *out = K_DCT1;
+  else if (a == -1 && b == -1) *out = K_DST1;
+  else if (a == 1 && b == -1) *out = K_DCT3;
+  else *out = K_DST3;
+  return 0;
+}
+
+void factor(int L, std::vector<int>& r) {
+  r.clear();
+  while (L % 8 == 0 && L > 8) { r.push_back(8); L /= 8; }
+  if (L == 8) { r.push_back(8); L = 1; }
+  while (L % 4 == 0) { r.push_back(4); L /= 4; }
+  while (L % 2 == 0) { r.push_back(2); L /= 2; }
+  while (L % 3 == 0) { r.push_back(3); L /= 3; }
+  while (L % 5 == 0) { r.push_back(5); L /= 5; }
+  for (int p = 7; L > 1; p += 2)
+    while (L % p == 0) { r.push_back(p); L /= p; }
+}
+
+int choose_F(int L, int rbytes, int packed_cap) {
+  const size_t per = 2 * (size_t)(L + 4) * 2 * rbytes;
+  int F = (int)std::max<size_t>(1, 65536 / per);
+  F = std::min(F, packed_cap);
+  return std::max(F, 1);
+}
+
+int make_geometry(const fm_plan_desc* d, Geometry& g) {
+  if (!d) return fail(FM_E_INVALID_ARG, "null descriptor");
+  for (int i = 0; i < 3; ++i) {
+    if (d->n[i] < 2) return fail(FM_E_INVALID_ARG, "each grid extent must be >= 2 voxels");
+    if (d->n[i] > 4096) return fail(FM_E_UNSUPPORTED, "grid extent above 4096 voxels");
+    g.n[i] = d->n[i];
+    g.N[i] = d->n[i] + 1;
+  }
+  if (!(d->h > 0)) return fail(FM_E_INVALID_ARG, "voxel size must be positive");
+  if (d->scheme != FM_HEX1 && d->scheme != FM_TETRA2) return fail(FM_E_INVALID_ARG, "unknown scheme");
+  if (d->green != FM_GREEN_B0 && d->green != FM_GREEN_2MU0) return fail(FM_E_UNSUPPORTED, "unsupported Green operator");
+  if (d->prec != FM_FP64 && d->prec != FM_FP32_MIXED) return fail(FM_E_INVALID_ARG, "unknown precision");
+  if (!(d->mu0 > 0) || d->lambda0 < 0) return fail(FM_E_INVALID_ARG, "reference medium needs mu0 > 0, lambda0 >= 0");
+  if (d->aa_depth < 1 || d->aa_depth > MAX_DEPTH) return fail(FM_E_INVALID_ARG, "aa_depth must be in 1..4");
+  if (d->aa_period < 1) return fail(FM_E_INVALID_ARG, "aa_period must be >= 1");
+  if (d->max_iter < 1) return fail(FM_E_INVALID_ARG, "max_iter must be >= 1");
+  if (d->max_materials < 1 || d->max_materials > 65535) return fail(FM_E_INVALID_ARG, "max_materials must be in 1..65535");
+  for (int q = 0; q < 3; ++q)
+    for (int i = 0; i < 3; ++i) {
+      for (int a = 0; a < 2; ++a)
+        if (d->bc[q][i][a] < 0 || d->bc[q][i][a] > 2) return fail(FM_E_BC, "unknown boundary condition code");
+      if (kind_of(d->bc[q][i][0], d->bc[q][i][1], &g.kinds[q][i]))
+        return fail(FM_E_BC, "periodic condition must hold on both opposite faces");
+    }
+  g.Nn = (int64_t)g.N[0] * g.N[1] * g.N[2];
+  g.Nv = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  g.nppv = d->scheme == FM_TETRA2 ? 2 : 1;
+  g.rbytes = d->prec == FM_FP64 ? 8 : 4;
+  g.depth = d->aa_depth;
+  for (int q = 0; q < 3; ++q) {
+    bool cx = false;
+    for (int a = 0; a < 3; ++a) {
+      const int k = g.kinds[q][a], n = g.n[a];
+      if (k == K_DFT) { g.M[q][a] = cx ? n : n / 2 + 1; cx = true; }
+      else g.M[q][a] = n_freq(k, n);
+      g.cplx[q][a] = cx;
+      g.L[q][a] = ext_len(k, n);
+      if (g.L[q][a] > 8192) return fail(FM_E_UNSUPPORTED, "pencil too long for one LDS transform");
+    }
+    g.s1[q] = (int64_t)g.M[q][0] * g.N[1] * g.N[2] * (g.cplx[q][0] ? 2 : 1);
+    g.s2[q] = (int64_t)g.M[q][0] * g.M[q][1] * g.N[2] * (g.cplx[q][1] ? 2 : 1);
+    g.F[q][0] = choose_F(g.L[q][0], g.rbytes, 16);
+    g.F[q][4] = g.F[q][0];
+    g.F[q][1] = choose_F(g.L[q][1], g.rbytes, 16);
+    g.F[q][3] = g.F[q][1];
+    g.F[q][2] = choose_F(g.L[q][2], g.rbytes, 16);
+  }
+  g.ntile_s = (int)cdiv(g.Nv, 256);
+  g.ntile_d = (int)cdiv(g.Nn, 256);
+  return 0;
+}
+
+// Layout of a plan workspace: offsets of every buffer.
+struct Layout {
+  size_t ctrl, log, uf, Dring, dring, sig, specA, specB, mat, mlaw, mtab, state, part_s, part_d, part_g,
+      tw, gtab, group, total;
+  size_t tw_off[3][3];
+  size_t g_off[3][3];   // green tables per comp, axis: s2 (M doubles), c2 (M doubles), flags (M bytes)
+  size_t group_bytes;
+};
+
+size_t group_bytes_for(int nsolves, int64_t tiles_total[7]);
+
+void tiles_of(const Geometry& g, int64_t t[7]) {
+  // stress, div, xfwd, yfwd, z, yinv, xinv
+  t[0] = g.ntile_s;
+  t[1] = g.ntile_d;
+  t[2] = t[3] = t[4] = t[5] = t[6] = 0;
+  for (int q = 0; q < 3; ++q) {
+    const int rows = g.N[1] * g.N[2];
+    t[2] += cdiv(rows, 2 * g.F[q][0]);
+    t[6] += cdiv(rows, 2 * g.F[q][4]);
+    const int coly = g.cplx[q][0] ? g.F[q][1] : 2 * g.F[q][1];
+    t[3] += cdiv(g.M[q][0], coly) * g.N[2];
+    t[5] += cdiv(g.M[q][0], coly) * g.N[2];
+    const int colz = g.cplx[q][1] ? g.F[q][2] : 2 * g.F[q][2];
+    t[4] += cdiv(g.M[q][0], colz) * g.M[q][1];
+  }
+}
+
+size_t group_bytes_for(int nsolves, int64_t tiles_total[7]) {
+  size_t b = 0;
+  b += align_up(sizeof(SolveDev) * nsolves);
+  b += align_up(sizeof(PassDesc) * nsolves * 15);
+  for (int i = 0; i < 7; ++i) b += align_up(sizeof(int2) * std::max<int64_t>(1, tiles_total[i]));
+  b += align_up(sizeof(int) * nsolves);
+  return b;
+}
+
+void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align_up(std::max<size_t>(bytes, 1)); return r; };
+  const size_t R = g.rbytes;
+  L.ctrl = take(sizeof(Ctrl));
+  L.log = take(sizeof(LogEntry) * (size_t)(d->max_iter + 2));
+  L.uf = take(8 * 3 * (size_t)g.Nn);
+  L.Dring = take(R * g.depth * 3 * (size_t)g.Nn);
+  L.dring = take(R * g.depth * 3 * (size_t)g.Nn);
+  L.sig = take(R * 6 * g.nppv * (size_t)g.Nv);
+  L.specA = take(R * (size_t)(g.s1[0] + g.s1[1] + g.s1[2]));
+  L.specB = take(R * (size_t)(g.s2[0] + g.s2[1] + g.s2[2]));
+  L.mat = take(2 * (size_t)g.Nv);
+  L.mlaw = take(4 * (size_t)d->max_materials);
+  L.mtab = take(R * MT_STRIDE * (size_t)d->max_materials);
+  L.state = d->with_state ? take(R * 7 * g.nppv * (size_t)g.Nv) : 0;
+  L.part_s = take(8 * NPART_S * (size_t)g.ntile_s);
+  L.part_d = take(8 * (size_t)g.ntile_d);
+  L.part_g = take(8 * NGRAM * (size_t)g.ntile_d);
+  for (int q = 0; q < 3; ++q)
+    for (int a = 0; a < 3; ++a) L.tw_off[q][a] = take(2 * R * (size_t)g.L[q][a]);
+  for (int q = 0; q < 3; ++q)
+    for (int a = 0; a < 3; ++a) L.g_off[q][a] = take(17 * (size_t)g.M[q][a]);
+  int64_t t[7];
+  tiles_of(g, t);
+  L.group_bytes = group_bytes_for(1, t);
+  L.group = take(L.group_bytes);
+  L.total = o + ALIGN;   // slack for base alignment
+}
+
+// ---------------------------------------------------------------------------
+// Host-side material tables
+// ---------------------------------------------------------------------------
+void quat_rot(const double* q, double R[3][3]) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  const double nrm = std::sqrt(w * w + x * x + y * y + z * z);
+  w /= nrm; x /= nrm; y /= nrm; z /= nrm;
+  R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z); R[0][2] = 2 * (x * z + w * y);
+  R[1][0] = 2 * (x * y + w * z); R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
+  R[2][0] = 2 * (x * z - w * y); R[2][1] = 2 * (y * z + w * x); R[2][2] = 1 - 2 * (x * x + y * y);
+}
+
+const int MI[6] = {0, 1, 2, 1, 0, 0}, MJ[6] = {0, 1, 2, 2, 2, 1};
+
+// Rotated cubic stiffness in Mandel form.
+void cubic_mandel(double C11, double C12, double C44, const double R[3][3], double out[36]) {
+  auto Cc = [&](int i, int j, int k, int l) {
+    double v = C12 * (i == j) * (k == l) + C44 * ((i == k) * (j == l) + (i == l) * (j == k));
+    if (i == j && j == k && k == l) v += C11 - C12 - 2 * C44;
+    return v;
+  };
+  double Cr[3][3][3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+          double s = 0;
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+              for (int c = 0; c < 3; ++c)
+                for (int e = 0; e < 3; ++e) s += R[i][a] * R[j][b] * R[k][c] * R[l][e] * Cc(a, b, c, e);
+          Cr[i][j][k][l] = s;
+        }
+  const double w[6] = {1, 1, 1, std::sqrt(2.0), std::sqrt(2.0), std::sqrt(2.0)};
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) out[a * 6 + b] = w[a] * w[b] * Cr[MI[a]][MJ[a]][MI[b]][MJ[b]];
+}
+
+bool invert6(const double* A, double* out) {
+  double M[6][12];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 12; ++j) M[i][j] = j < 6 ? A[i * 6 + j] : (j - 6 == i);
+  for (int p = 0; p < 6; ++p) {
+    int piv = p;
+    for (int q = p + 1; q < 6; ++q) if (std::fabs(M[q][p]) > std::fabs(M[piv][p])) piv = q;
+    if (std::fabs(M[piv][p]) < 1e-300) return false;
+    for (int c = 0; c < 12; ++c) std::swap(M[p][c], M[piv][c]);
+    const double ip = 1.0 / M[p][p];
+    for (int c = 0; c < 12; ++c) M[p][c] *= ip;
+    for (int q = 0; q < 6; ++q)
+      if (q != p) {
+        const double f = M[q][p];
+        for (int c = 0; c < 12; ++c) M[q][c] -= f * M[p][c];
+      }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) out[i * 6 + j] = M[i][j + 6];
+  return true;
+}
+
+// 12 FCC systems {111}<110>: unit plane normals and slip directions.
+void fcc_systems(double m[12][3], double nrm[12][3]) {
+  const int N4[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+  int cnt = 0;
+  for (int p = 0; p < 4; ++p) {
+    for (int a = 0; a < 3; ++a)
+      for (int b = a + 1; b < 3; ++b)
+        for (int sb = 1; sb >= -1; sb -= 2) {
+          int dvec[3] = {0, 0, 0};
+          dvec[a] = 1; dvec[b] = sb;
+          if (dvec[0] * N4[p][0] + dvec[1] * N4[p][1] + dvec[2] * N4[p][2] != 0) continue;
+          for (int i = 0; i < 3; ++i) {
+            m[cnt][i] = dvec[i] / std::sqrt(2.0);
+            nrm[cnt][i] = N4[p][i] / std::sqrt(3.0);
+          }
+          ++cnt;
+        }
+  }
+}
+
+int material_entry(const fm_material& mt, double* e /* MT_STRIDE */) {
+  std::fill(e, e + MT_STRIDE, 0.0);
+  switch (mt.law) {
+    case FM_LAW_ISO:
+      if (mt.p[0] < 0 || mt.p[1] < 0) return fail(FM_E_INVALID_ARG, "isotropic moduli must be >= 0");
+      e[0] = mt.p[0]; e[1] = mt.p[1];
+      return LAW_ISO;
+    case FM_LAW_CUBIC: {
+      double R[3][3];
+      quat_rot(mt.quat, R);
+      cubic_mandel(mt.p[0], mt.p[1], mt.p[2], R, e);
+      return LAW_ANISO;
+    }
+    case FM_LAW_J2:
+      if (!(mt.p[1] > 0) || !(mt.p[2] >= 0) || !(mt.p[3] >= 0)) return fail(FM_E_INVALID_ARG, "J2 needs mu > 0, sy0 >= 0, H >= 0");
+      e[0] = mt.p[0]; e[1] = mt.p[1]; e[2] = mt.p[2]; e[3] = mt.p[3];
+      return LAW_J2;
+    case FM_LAW_CP: {
+      double R[3][3];
+      quat_rot(mt.quat, R);
+      cubic_mandel(mt.p[0], mt.p[1], mt.p[2], R, e);
+      if (!invert6(e, e + 36)) return fail(FM_E_INVALID_ARG, "singular crystal stiffness");
+      double m[12][3], nn[12][3];
+      fcc_systems(m, nn);
+      for (int s = 0; s < 12; ++s) {
+        double ms[3] = {0, 0, 0}, ns[3] = {0, 0, 0};
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) { ms[i] += R[i][j] * m[s][j]; ns[i] += R[i][j] * nn[s][j]; }
+        for (int a = 0; a < 6; ++a) {
+          const int i = MI[a], j = MJ[a];
+          const double pij = 0.5 * (ms[i] * ns[j] + ms[j] * ns[i]);
+          e[72 + s * 6 + a] = (a < 3 ? 1.0 : std::sqrt(2.0)) * pij;
+        }
+      }
+      if (!(mt.p[3] > 0) || !(mt.p[4] >= 1) || !(mt.p[5] > 0) || !(mt.p[6] > mt.p[5]) || !(mt.p[7] >= 0))
+        return fail(FM_E_INVALID_ARG, "crystal plasticity parameters out of range");
+      e[144] = mt.p[3]; e[145] = mt.p[4]; e[146] = mt.p[5]; e[147] = mt.p[6]; e[148] = mt.p[7];
+      return LAW_CP;
+    }
+    default:
+      return fail(FM_E_INVALID_ARG, "unknown law");
+  }
+}
+
+__global__ void k_mat_convert(const int32_t* in, uint16_t* out, int64_t n, int nmat, int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  int v = in[i];
+  if (v < 0 || v >= nmat) { atomicOr(bad, 1); v = 0; }
+  out[i] = (uint16_t)v;
+}
+
+__global__ void k_cast_f(const double* in, float* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+__global__ void k_cast_d(const float* in, double* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
+__global__ void k_copy_u16(const uint16_t* in, uint16_t* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct Group;
+
+struct fm_plan {
+  fm_plan_desc d;
+  Geometry g;
+  Layout lay;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  SolveDev sd{};           // host image of the device descriptor
+  PassDesc pd[3][5]{};     // host images
+  bool material_set = false;
+  int n_mat = 0;
+  int64_t total_iters = 0;
+  Group* self = nullptr;   // single-plan group
+  // per-solve bookkeeping used by batch / server drivers
+  int cur_step = 0;
+  int rc = FM_OK;
+};
+
+// A set of solves advanced together.
+struct Group {
+  int prec = 0;
+  int ns = 0;
+  hipStream_t stream = nullptr;
+  SolveDev* S = nullptr;
+  PassDesc* P = nullptr;
+  int2* wl[7]{};
+  int64_t nwl[7]{};
+  int* ids = nullptr;
+  size_t lds[5]{};
+};
+
+namespace {
+
+void fill_pass_descs(fm_plan* p) {
+  const Geometry& g = p->g;
+  const size_t R = g.rbytes;
+  char* ws = p->ws;
+  int64_t offA = 0, offB = 0;
+  for (int q = 0; q < 3; ++q) {
+    void* A = ws + p->lay.specA + R * offA;
+    void* B = ws + p->lay.specB + R * offB;
+    offA += g.s1[q];
+    offB += g.s2[q];
+    const int M0 = g.M[q][0], M1 = g.M[q][1];
+    const int c1 = g.cplx[q][0], c2 = g.cplx[q][1];
+    std::vector<int> rad;
+    for (int pass = 0; pass < 5; ++pass) {
+      PassDesc& d = p->pd[q][pass];
+      std::memset(&d, 0, sizeof(d));
+      d.solve = 0;
+      d.q = q;
+      const int axis = pass == 0 || pass == 4 ? 0 : (pass == 2 ? 2 : 1);
+      d.kind = g.kinds[q][axis];
+      d.n = g.n[axis];
+      d.L = g.L[q][axis];
+      factor(d.L, rad);
+      d.nrad = (int)rad.size();
+      for (int i = 0; i < d.nrad; ++i) d.rad[i] = rad[i];
+      d.F = g.F[q][pass];
+      d.tw = ws + p->lay.tw_off[q][axis];
+      switch (pass) {
+        case 0:   // x forward: D ring rows -> A (M0 per row)
+          d.cplx_in = 0; d.cplx_out = c1; d.packed = 1;
+          d.len_in = g.N[0]; d.len_out = M0;
+          d.n_p0 = g.N[1] * g.N[2];
+          d.cols = 2 * d.F;
+          d.tiles_p0 = (int)cdiv(d.n_p0, d.cols);
+          d.in_s1 = g.N[0]; d.out_s1 = M0;
+          d.out = A;
+          d.ring = ws + p->lay.Dring + R * (size_t)q * g.Nn;
+          d.ring_stride = 3 * g.Nn;
+          break;
+        case 4:   // x inverse: A -> u update
+          d.cplx_in = c1; d.cplx_out = 0; d.packed = 1;
+          d.len_in = M0; d.len_out = g.N[0];
+          d.n_p0 = g.N[1] * g.N[2];
+          d.cols = 2 * d.F;
+          d.tiles_p0 = (int)cdiv(d.n_p0, d.cols);
+          d.in_s1 = M0; d.out_s1 = g.N[0];
+          d.in = A;
+          d.ring = ws + p->lay.dring + R * (size_t)q * g.Nn;
+          d.ring_stride = 3 * g.Nn;
+          d.uf = (double*)(ws + p->lay.uf) + (size_t)q * g.Nn;
+          break;
+        case 1:   // y forward: A (M0, N1, N2) -> B (M0, M1, N2)
+          d.cplx_in = c1; d.cplx_out = c2; d.packed = !c1;
+          d.len_in = g.N[1]; d.len_out = M1;
+          d.n_p0 = M0; d.n_p1 = g.N[2];
+          d.cols = d.packed ? 2 * d.F : d.F;
+          d.tiles_p0 = (int)cdiv(M0, d.cols);
+          d.in_sa = M0; d.in_s1 = (int64_t)M0 * g.N[1];
+          d.out_sa = M0; d.out_s1 = (int64_t)M0 * M1;
+          d.in = A; d.out = B;
+          break;
+        case 3:   // y inverse: B -> A
+          d.cplx_in = c2; d.cplx_out = c1; d.packed = !c1;
+          d.len_in = M1; d.len_out = g.N[1];
+          d.n_p0 = M0; d.n_p1 = g.N[2];
+          d.cols = d.packed ? 2 * d.F : d.F;
+          d.tiles_p0 = (int)cdiv(M0, d.cols);
+          d.in_sa = M0; d.in_s1 = (int64_t)M0 * M1;
+          d.out_sa = M0; d.out_s1 = (int64_t)M0 * g.N[1];
+          d.in = B; d.out = A;
+          break;
+        case 2:   // z forward + Green + inverse, in place in B (M0, M1, N2)
+          d.cplx_in = c2; d.cplx_out = c2; d.packed = !c2;
+          d.len_in = g.N[2]; d.len_out = g.N[2];
+          d.n_p0 = M0; d.n_p1 = M1;
+          d.cols = d.packed ? 2 * d.F : d.F;
+          d.tiles_p0 = (int)cdiv(M0, d.cols);
+          d.in_sa = d.out_sa = (int64_t)M0 * M1;
+          d.in_s1 = d.out_s1 = M0;
+          d.in = B; d.out = B;
+          for (int a = 0; a < 3; ++a) {
+            char* t = ws + p->lay.g_off[q][a];
+            d.gs2[a] = (const double*)t;
+            d.gc2[a] = (const double*)(t + 8 * (size_t)g.M[q][a]);
+            d.gfl[a] = (const uint8_t*)(t + 16 * (size_t)g.M[q][a]);
+          }
+          d.scheme = p->d.scheme;
+          d.green_lam = p->d.green == FM_GREEN_B0;
+          d.h = p->d.h; d.lam0 = p->d.lambda0; d.mu0 = p->d.mu0;
+          break;
+      }
+    }
+  }
+}
+
+int upload_tables(fm_plan* p) {
+  const Geometry& g = p->g;
+  char* ws = p->ws;
+  for (int q = 0; q < 3; ++q)
+    for (int a = 0; a < 3; ++a) {
+      const int L = g.L[q][a];
+      if (g.rbytes == 8) {
+        std::vector<double> t(2 * L);
+        for (int i = 0; i < L; ++i) {
+          const long double ang = -2.0L * 3.14159265358979323846264338327950288L * i / L;
+          t[2 * i] = (double)cosl(ang); t[2 * i + 1] = (double)sinl(ang);
+        }
+        HIPCHK(hipMemcpyAsync(ws + p->lay.tw_off[q][a], t.data(), 8 * t.size(), hipMemcpyHostToDevice, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+      } else {
+        std::vector<float> t(2 * L);
+        for (int i = 0; i < L; ++i) {
+          const long double ang = -2.0L * 3.14159265358979323846264338327950288L * i / L;
+          t[2 * i] = (float)cosl(ang); t[2 * i + 1] = (float)sinl(ang);
+        }
+        HIPCHK(hipMemcpyAsync(ws + p->lay.tw_off[q][a], t.data(), 4 * t.size(), hipMemcpyHostToDevice, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+      }
+      // Green tables: sin^2(xi/2), cos^2(xi/2) and index flags (xi = 0, xi = pi)
+      const int M = g.M[q][a], n = g.n[a], k = g.kinds[q][a];
+      std::vector<char> buf(17 * (size_t)M);
+      double* s2 = (double*)buf.data();
+      double* c2 = s2 + M;
+      uint8_t* fl = (uint8_t*)(c2 + M);
+      for (int i = 0; i < M; ++i) {
+        long double xi;
+        switch (k) {
+          case K_DFT: xi = 2.0L * M_PIl * i / n; break;
+          case K_DCT1: xi = M_PIl * i / n; break;
+          case K_DST1: xi = M_PIl * (i + 1) / n; break;
+          default: xi = M_PIl * (i + 0.5L) / n; break;
+        }
+        uint8_t f = 0;
+        if ((k == K_DFT || k == K_DCT1) && i == 0) f |= 1;
+        if ((k == K_DFT && n % 2 == 0 && i == n / 2) || (k == K_DCT1 && i == n)) f |= 2;
+        long double s = sinl(0.5L * xi), c = cosl(0.5L * xi);
+        if (f & 1) { s = 0; c = 1; }
+        if (f & 2) { s = 1; c = 0; }
+        s2[i] = (double)(s * s);
+        c2[i] = (double)(c * c);
+        fl[i] = f;
+      }
+      HIPCHK(hipMemcpyAsync(ws + p->lay.g_off[q][a], buf.data(), buf.size(), hipMemcpyHostToDevice, p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+    }
+  return 0;
+}
+
+// Build a group's device arrays for `plans` inside [dev, dev+bytes).
+int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes, hipStream_t stream) {
+  if (ns < 1) return fail(FM_E_INVALID_ARG, "empty group");
+  G.prec = plans[0]->d.prec;
+  G.ns = ns;
+  G.stream = stream;
+  int64_t t[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < ns; ++i) {
+    if (plans[i]->d.prec != G.prec) return fail(FM_E_INVALID_ARG, "a batch must share one precision");
+    int64_t ti[7];
+    tiles_of(plans[i]->g, ti);
+    for (int k = 0; k < 7; ++k) t[k] += ti[k];
+  }
+  const size_t need = group_bytes_for(ns, t);
+  if (need > bytes) return fail(FM_E_WORKSPACE, "group workspace too small");
+  size_t o = 0;
+  G.S = (SolveDev*)(dev + o); o += align_up(sizeof(SolveDev) * ns);
+  G.P = (PassDesc*)(dev + o); o += align_up(sizeof(PassDesc) * ns * 15);
+  for (int k = 0; k < 7; ++k) { G.wl[k] = (int2*)(dev + o); o += align_up(sizeof(int2) * std::max<int64_t>(1, t[k])); }
+  G.ids = (int*)(dev + o);
+  std::vector<SolveDev> S(ns);
+  std::vector<PassDesc> P(ns * 15);
+  std::vector<int2> wl[7];
+  std::vector<int> ids(ns);
+  for (int k = 0; k < 5; ++k) G.lds[k] = 0;
+  for (int i = 0; i < ns; ++i) {
+    fm_plan* p = plans[i];
+    S[i] = p->sd;
+    ids[i] = i;
+    for (int ty = 0; ty < p->g.ntile_s; ++ty) wl[0].push_back(make_int2(i, ty));
+    for (int ty = 0; ty < p->g.ntile_d; ++ty) wl[1].push_back(make_int2(i, ty));
+    for (int q = 0; q < 3; ++q)
+      for (int pass = 0; pass < 5; ++pass) {
+        PassDesc d = p->pd[q][pass];
+        d.solve = i;
+        const int di = i * 15 + q * 5 + pass;
+        P[di] = d;
+        int64_t ntiles = pass == 0 || pass == 4 ? d.tiles_p0 : (int64_t)d.tiles_p0 * d.n_p1;
+        const int wk = pass == 0 ? 2 : pass == 1 ? 3 : pass == 2 ? 4 : pass == 3 ? 5 : 6;
+        for (int64_t ty = 0; ty < ntiles; ++ty) wl[wk].push_back(make_int2(di, (int)ty));
+        const size_t lds = 2 * (size_t)d.F * (d.L + 4) * 2 * p->g.rbytes;
+        G.lds[pass] = std::max(G.lds[pass], lds);
+      }
+  }
+  HIPCHK(hipMemcpyAsync(G.S, S.data(), sizeof(SolveDev) * ns, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(G.P, P.data(), sizeof(PassDesc) * ns * 15, hipMemcpyHostToDevice, stream));
+  for (int k = 0; k < 7; ++k) {
+    G.nwl[k] = (int64_t)wl[k].size();
+    if (!wl[k].empty())
+      HIPCHK(hipMemcpyAsync(G.wl[k], wl[k].data(), sizeof(int2) * wl[k].size(), hipMemcpyHostToDevice, stream));
+  }
+  HIPCHK(hipMemcpyAsync(G.ids, ids.data(), sizeof(int) * ns, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return 0;
+}
+
+template <typename R>
+int set_lds_limits() {
+  static bool done = false;
+  if (done) return 0;
+  const int big = 160 * 1024;
+  HIPCHK(hipFuncSetAttribute((const void*)k_xfwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_xinv<R>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_strided<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_strided<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_strided<R, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  done = true;
+  return 0;
+}
+
+template <typename R>
+int launch_iteration(const Group& G) {
+  hipStream_t st = G.stream;
+  if (G.nwl[0]) hipLaunchKernelGGL(k_stress<R>, dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
+  if (G.nwl[1]) hipLaunchKernelGGL(k_div<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]);
+  hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids);
+  if (G.nwl[1]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]);
+  hipLaunchKernelGGL(k_alpha, dim3(G.ns), dim3(256), 0, st, G.S, G.ids);
+  if (G.nwl[2]) hipLaunchKernelGGL(k_xfwd<R>, dim3(G.nwl[2]), dim3(256), G.lds[0], st, G.P, G.wl[2], G.S);
+  if (G.nwl[3]) hipLaunchKernelGGL((k_strided<R, 0>), dim3(G.nwl[3]), dim3(256), G.lds[1], st, G.P, G.wl[3], G.S);
+  if (G.nwl[4]) hipLaunchKernelGGL((k_strided<R, 2>), dim3(G.nwl[4]), dim3(256), G.lds[2], st, G.P, G.wl[4], G.S);
+  if (G.nwl[5]) hipLaunchKernelGGL((k_strided<R, 1>), dim3(G.nwl[5]), dim3(256), G.lds[3], st, G.P, G.wl[5], G.S);
+  if (G.nwl[6]) hipLaunchKernelGGL(k_xinv<R>, dim3(G.nwl[6]), dim3(256), G.lds[4], st, G.P, G.wl[6], G.S);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int launch_iterations(const Group& G, int count) {
+  for (int i = 0; i < count; ++i) {
+    const int rc = G.prec == FM_FP64 ? launch_iteration<double>(G) : launch_iteration<float>(G);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+template <typename R>
+int launch_commit_t(fm_plan* p) {
+  const Group& G = *p->self;
+  hipLaunchKernelGGL(k_stress<R>, dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0], 1);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int launch_commit(fm_plan* p) {
+  return p->d.prec == FM_FP64 ? launch_commit_t<double>(p) : launch_commit_t<float>(p);
+}
+
+Ctrl* dev_ctrl(fm_plan* p) { return (Ctrl*)(p->ws + p->lay.ctrl); }
+LogEntry* dev_log(fm_plan* p) { return (LogEntry*)(p->ws + p->lay.log); }
+
+// Start increment `t` of a plan: upload the control block.
+int begin_step(fm_plan* p, const fm_load_step& st, int t, const Ctrl* prev) {
+  Ctrl c;
+  std::memset(&c, 0, sizeof(c));
+  c.m = 0;
+  c.status = ST_RUNNING;
+  c.step = t;
+  c.max_iter = p->d.max_iter;
+  c.depth = p->d.aa_depth;
+  c.period = p->d.aa_period;
+  c.dt = st.dt;
+  c.tol = p->d.tol;
+  c.lam0 = p->d.lambda0;
+  c.mu0 = p->d.mu0;
+  for (int q = 0; q < 3; ++q) {
+    c.c[q] = st.c[q];
+    for (int l = 0; l < 3; ++l) {
+      c.G[q * 3 + l] = st.G[q][l];
+      for (int m = 0; m < 3; ++m) c.H[(q * 3 + l) * 3 + m] = 0.5 * (st.H[q][l][m] + st.H[q][m][l]);
+    }
+  }
+  for (int i = 0; i < 6; ++i) {
+    c.mixed_mask[i] = st.mixed_mask[i] != 0;
+    c.mixed_target[i] = st.mixed_target[i];
+  }
+  if (prev && t > 0) {
+    // stress-controlled components continue from the previous increment
+    for (int i = 0; i < 6; ++i)
+      if (c.mixed_mask[i]) {
+        const int a = MI[i], b = MJ[i];
+        c.G[a * 3 + b] = prev->G[a * 3 + b];
+        c.G[b * 3 + a] = prev->G[b * 3 + a];
+      }
+  }
+  HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, p->stream));
+  return 0;
+}
+
+int set_outputs(fm_plan* p, fm_outputs* out) {
+  p->sd.out_u = out ? out->u : nullptr;
+  p->sd.out_eps = out ? out->eps : nullptr;
+  p->sd.out_sig = out ? out->sig : nullptr;
+  HIPCHK(hipMemcpyAsync(p->self->S, &p->sd, sizeof(SolveDev), hipMemcpyHostToDevice, p->stream));
+  return 0;
+}
+
+int finish_step(fm_plan* p, const Ctrl& c, int t, bool last, fm_outputs* out, fm_iter_log* log) {
+  // commit internal variables; final increment also writes the field outputs
+  if (last && out && (out->eps || out->sig || out->u)) {
+    int rc = set_outputs(p, out);
+    if (rc) return rc;
+  }
+  int rc = launch_commit(p);
+  if (rc) return rc;
+  if (last && out && out->u) {
+    hipLaunchKernelGGL(k_out_u, dim3(cdiv(p->g.Nn, 256)), dim3(256), 0, p->stream, p->self->S, 0);
+    HIPCHK(hipGetLastError());
+  }
+  if (last && out && (out->eps || out->sig || out->u)) {
+    rc = set_outputs(p, nullptr);
+    if (rc) return rc;
+  }
+  if (out && out->macro_sigma)
+    for (int i = 0; i < 6; ++i) out->macro_sigma[t * 6 + i] = c.macro[i];
+  if (out && out->iters) out->iters[t] = c.m;
+  if (out && out->converged) out->converged[t] = c.status == ST_CONVERGED;
+  p->total_iters += c.m;
+  if (log && log->entries && c.log_count > 0) {
+    std::vector<LogEntry> le(c.log_count);
+    HIPCHK(hipMemcpyAsync(le.data(), dev_log(p), sizeof(LogEntry) * c.log_count, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (int i = 0; i < c.log_count && log->count < log->capacity; ++i) {
+      fm_iter_entry& e = log->entries[log->count++];
+      e.step = t; e.iter = i; e.err = le[i].err; e.aa_applied = le[i].aa != 0; e.pad_ = 0;
+      for (int k = 0; k < 6; ++k) e.macro_sigma[k] = le[i].macro[k];
+    }
+  }
+  return 0;
+}
+
+int read_ctrl(fm_plan* p, Ctrl& c) {
+  HIPCHK(hipMemcpyAsync(&c, dev_ctrl(p), sizeof(Ctrl), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* fm_last_error(void) { return g_err.c_str(); }
+
+size_t fm_workspace_bytes(const fm_plan_desc* desc) {
+  Geometry g;
+  if (make_geometry(desc, g)) return 0;
+  Layout L;
+  make_layout(desc, g, L);
+  return L.total;
+}
+
+int fm_plan_create(const fm_plan_desc* desc, void* d_workspace, size_t ws_bytes, void* hip_stream, fm_plan** out) {
+  if (!out) return fail(FM_E_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  std::unique_ptr<fm_plan> p(new fm_plan());
+  int rc = make_geometry(desc, p->g);
+  if (rc) return rc;
+  p->d = *desc;
+  make_layout(desc, p->g, p->lay);
+  if (!d_workspace) return fail(FM_E_WORKSPACE, "null workspace");
+  const uintptr_t base = ((uintptr_t)d_workspace + ALIGN - 1) / ALIGN * ALIGN;
+  if (ws_bytes < p->lay.total) return fail(FM_E_WORKSPACE, "workspace smaller than fm_workspace_bytes()");
+  p->ws = (char*)base;
+  p->stream = (hipStream_t)hip_stream;
+  rc = p->d.prec == FM_FP64 ? set_lds_limits<double>() : set_lds_limits<float>();
+  if (rc) return rc;
+  // device descriptor
+  SolveDev& s = p->sd;
+  std::memset(&s, 0, sizeof(s));
+  const Geometry& g = p->g;
+  for (int i = 0; i < 3; ++i) { s.n[i] = g.n[i]; s.N[i] = g.N[i]; }
+  s.Nn = g.Nn; s.Nv = g.Nv;
+  s.scheme = desc->scheme; s.nppv = g.nppv; s.depth = g.depth; s.has_state = desc->with_state ? 1 : 0;
+  for (int q = 0; q < 3; ++q)
+    for (int a = 0; a < 3; ++a) s.kinds[q][a] = g.kinds[q][a];
+  s.h = desc->h; s.lam0 = desc->lambda0; s.mu0 = desc->mu0;
+  char* ws = p->ws;
+  s.uf = (double*)(ws + p->lay.uf);
+  s.Dring = ws + p->lay.Dring;
+  s.dring = ws + p->lay.dring;
+  s.sig = ws + p->lay.sig;
+  s.mat = (const uint16_t*)(ws + p->lay.mat);
+  s.mtab = ws + p->lay.mtab;
+  s.mlaw = (const int32_t*)(ws + p->lay.mlaw);
+  s.state = desc->with_state ? ws + p->lay.state : nullptr;
+  s.ctrl = (Ctrl*)(ws + p->lay.ctrl);
+  s.log = (LogEntry*)(ws + p->lay.log);
+  s.part_s = (double*)(ws + p->lay.part_s);
+  s.part_d = (double*)(ws + p->lay.part_d);
+  s.part_g = (double*)(ws + p->lay.part_g);
+  s.ntile_s = g.ntile_s; s.ntile_d = g.ntile_d;
+  fill_pass_descs(p.get());
+  rc = upload_tables(p.get());
+  if (rc) return rc;
+  Ctrl c;
+  std::memset(&c, 0, sizeof(c));
+  c.status = ST_IDLE;
+  HIPCHK(hipMemcpyAsync(dev_ctrl(p.get()), &c, sizeof(c), hipMemcpyHostToDevice, p->stream));
+  p->self = new Group();
+  rc = build_group(*p->self, (fm_plan* const*)&p, 1, ws + p->lay.group, p->lay.group_bytes, p->stream);
+  if (rc) { delete p->self; return rc; }
+  *out = p.release();
+  return FM_OK;
+}
+
+void fm_plan_destroy(fm_plan* plan) {
+  if (!plan) return;
+  delete plan->self;
+  delete plan;
+}
+
+int64_t fm_plan_total_iterations(const fm_plan* plan) { return plan ? plan->total_iters : -1; }
+
+int fm_set_material(fm_plan* p, const int32_t* d_mat_id, int32_t n_mat, const fm_material* table) {
+  if (!p || !d_mat_id || !table || n_mat < 1) return fail(FM_E_INVALID_ARG, "null or empty material arguments");
+  if (n_mat > p->d.max_materials) return fail(FM_E_CAPACITY, "more materials than max_materials");
+  const size_t R = p->g.rbytes;
+  std::vector<int32_t> laws(n_mat);
+  std::vector<double> e(MT_STRIDE);
+  std::vector<char> tab(R * MT_STRIDE * n_mat);
+  for (int i = 0; i < n_mat; ++i) {
+    const int law = material_entry(table[i], e.data());
+    if (law < 0) return law;
+    if ((law == LAW_J2 || law == LAW_CP) && !p->d.with_state)
+      return fail(FM_E_UNSUPPORTED, "J2 / CP materials need with_state = 1 in the plan");
+    laws[i] = law;
+    for (int k = 0; k < MT_STRIDE; ++k) {
+      if (R == 8) ((double*)tab.data())[(size_t)i * MT_STRIDE + k] = e[k];
+      else ((float*)tab.data())[(size_t)i * MT_STRIDE + k] = (float)e[k];
+    }
+  }
+  char* ws = p->ws;
+  HIPCHK(hipMemcpyAsync(ws + p->lay.mlaw, laws.data(), 4 * n_mat, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(ws + p->lay.mtab, tab.data(), tab.size(), hipMemcpyHostToDevice, p->stream));
+  int* bad = (int*)(ws + p->lay.part_d);   // scratch word
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), p->stream));
+  hipLaunchKernelGGL(k_mat_convert, dim3(cdiv(p->g.Nv, 256)), dim3(256), 0, p->stream, d_mat_id,
+                     (uint16_t*)(ws + p->lay.mat), p->g.Nv, n_mat, bad);
+  HIPCHK(hipGetLastError());
+  int hbad = 0;
+  HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  if (hbad) return fail(FM_E_INVALID_ARG, "material id out of range");
+  HIPCHK(hipMemsetAsync(ws + p->lay.uf, 0, 8 * 3 * (size_t)p->g.Nn, p->stream));
+  HIPCHK(hipMemsetAsync(ws + p->lay.dring, 0, R * p->g.depth * 3 * (size_t)p->g.Nn, p->stream));
+  if (p->d.with_state) HIPCHK(hipMemsetAsync(ws + p->lay.state, 0, R * 7 * p->g.nppv * (size_t)p->g.Nv, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->material_set = true;
+  p->n_mat = n_mat;
+  return FM_OK;
+}
+
+int fm_solve(fm_plan* p, const fm_load_step* steps, int32_t n_steps, fm_outputs* out, fm_iter_log* log) {
+  if (!p || !steps || n_steps < 1) return fail(FM_E_INVALID_ARG, "null plan or empty load path");
+  if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called before fm_solve");
+  if (log) log->count = 0;
+  p->total_iters = 0;
+  int result = FM_OK;
+  Ctrl prev;
+  bool have_prev = false;
+  for (int t = 0; t < n_steps; ++t) {
+    int rc = begin_step(p, steps[t], t, have_prev ? &prev : nullptr);
+    if (rc) return rc;
+    Ctrl c;
+    int chunk = 4;
+    while (true) {
+      rc = launch_iterations(*p->self, chunk);
+      if (rc) return rc;
+      rc = read_ctrl(p, c);
+      if (rc) return rc;
+      if (c.status != ST_RUNNING) break;
+      chunk = std::min(chunk * 2, 32);
+    }
+    if (c.status == ST_MAXITER) result = FM_W_NOT_CONVERGED;
+    rc = finish_step(p, c, t, t == n_steps - 1, out, log);
+    if (rc) return rc;
+    prev = c;
+    have_prev = true;
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return result;
+}
+
+int fm_apply_green(fm_plan* p, const double* d_x, double* d_w) {
+  if (!p || !d_x || !d_w) return fail(FM_E_INVALID_ARG, "null argument");
+  Ctrl c;
+  std::memset(&c, 0, sizeof(c));
+  c.status = ST_RUNNING;
+  c.depth = p->d.aa_depth;
+  c.n_d = 1; c.slot_d[0] = 0; c.alpha[0] = 1.0;
+  c.n_b = 0; c.slot_w = 0;
+  HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, p->stream));
+  const int64_t n3 = 3 * p->g.Nn;
+  if (p->d.prec == FM_FP64) {
+    HIPCHK(hipMemcpyAsync(p->ws + p->lay.Dring, d_x, 8 * n3, hipMemcpyDeviceToDevice, p->stream));
+  } else {
+    hipLaunchKernelGGL(k_cast_f, dim3(cdiv(n3, 256)), dim3(256), 0, p->stream, d_x, (float*)(p->ws + p->lay.Dring), n3);
+  }
+  HIPCHK(hipMemsetAsync(p->ws + p->lay.uf, 0, 8 * n3, p->stream));
+  const Group& G = *p->self;
+  hipStream_t st = p->stream;
+  if (p->d.prec == FM_FP64) {
+    hipLaunchKernelGGL(k_xfwd<double>, dim3(G.nwl[2]), dim3(256), G.lds[0], st, G.P, G.wl[2], G.S);
+    hipLaunchKernelGGL((k_strided<double, 0>), dim3(G.nwl[3]), dim3(256), G.lds[1], st, G.P, G.wl[3], G.S);
+    hipLaunchKernelGGL((k_strided<double, 2>), dim3(G.nwl[4]), dim3(256), G.lds[2], st, G.P, G.wl[4], G.S);
+    hipLaunchKernelGGL((k_strided<double, 1>), dim3(G.nwl[5]), dim3(256), G.lds[3], st, G.P, G.wl[5], G.S);
+    hipLaunchKernelGGL(k_xinv<double>, dim3(G.nwl[6]), dim3(256), G.lds[4], st, G.P, G.wl[6], G.S);
+  } else {
+    hipLaunchKernelGGL(k_xfwd<float>, dim3(G.nwl[2]), dim3(256), G.lds[0], st, G.P, G.wl[2], G.S);
+    hipLaunchKernelGGL((k_strided<float, 0>), dim3(G.nwl[3]), dim3(256), G.lds[1], st, G.P, G.wl[3], G.S);
+    hipLaunchKernelGGL((k_strided<float, 2>), dim3(G.nwl[4]), dim3(256), G.lds[2], st, G.P, G.wl[4], G.S);
+    hipLaunchKernelGGL((k_strided<float, 1>), dim3(G.nwl[5]), dim3(256), G.lds[3], st, G.P, G.wl[5], G.S);
+    hipLaunchKernelGGL(k_xinv<float>, dim3(G.nwl[6]), dim3(256), G.lds[4], st, G.P, G.wl[6], G.S);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(d_w, p->ws + p->lay.uf, 8 * n3, hipMemcpyDeviceToDevice, p->stream));
+  c.status = ST_IDLE;
+  HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return FM_OK;
+}
+
+int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double* d_D, double* err, double* macro) {
+  if (!p || !step || !d_uf || !d_D) return fail(FM_E_INVALID_ARG, "null argument");
+  if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called first");
+  int rc = begin_step(p, *step, 0, nullptr);
+  if (rc) return rc;
+  const int64_t n3 = 3 * p->g.Nn;
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.uf, d_uf, 8 * n3, hipMemcpyDeviceToDevice, p->stream));
+  const Group& G = *p->self;
+  hipStream_t st = p->stream;
+  if (p->d.prec == FM_FP64) {
+    hipLaunchKernelGGL(k_stress<double>, dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
+    hipLaunchKernelGGL(k_div<double>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]);
+  } else {
+    hipLaunchKernelGGL(k_stress<float>, dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
+    hipLaunchKernelGGL(k_div<float>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]);
+  }
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, G.S, G.ids);
+  HIPCHK(hipGetLastError());
+  if (p->d.prec == FM_FP64) {
+    HIPCHK(hipMemcpyAsync(d_D, p->ws + p->lay.Dring, 8 * n3, hipMemcpyDeviceToDevice, st));
+  } else {
+    hipLaunchKernelGGL(k_cast_d, dim3(cdiv(n3, 256)), dim3(256), 0, st, (const float*)(p->ws + p->lay.Dring), d_D, n3);
+  }
+  Ctrl c;
+  rc = read_ctrl(p, c);
+  if (rc) return rc;
+  if (err) *err = c.err;
+  if (macro) for (int i = 0; i < 6; ++i) macro[i] = c.macro[i];
+  c.status = ST_IDLE;
+  HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FM_OK;
+}
+
+}  // extern "C"
+
+#include "fm_batch.inc"
