@@ -211,6 +211,16 @@ int fm_apply_green(fm_plan* plan, const double* d_x, double* d_w);
 int fm_residual(fm_plan* plan, const fm_load_step* step, const double* d_uf, double* d_D,
                 double* err, double* macro);
 
+/* Per-kernel timing of the iteration (for roofline reporting): runs n_iter
+ * iterations of *step with the convergence test disabled, recording HIP
+ * events on the plan's stream around each of the FM_N_KERNELS launches, and
+ * writes the mean duration in milliseconds per kernel to ms[FM_N_KERNELS]
+ * (order: stress, div, control, gram, alpha, x-forward, y-forward,
+ * z-forward+Green+inverse, y-inverse, x-inverse+update).  Overwrites the
+ * plan's displacement. */
+#define FM_N_KERNELS 10
+int fm_profile_iterations(fm_plan* plan, const fm_load_step* step, int32_t n_iter, double* ms);
+
 /* Iterations performed by the last fm_solve / fm_batch_solve of this plan. */
 int64_t fm_plan_total_iterations(const fm_plan* plan);
 

@@ -86,6 +86,8 @@ EXPORTS = {
     "fm_apply_green": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fm_residual": (C.c_int, [C.c_void_p, C.POINTER(LoadStep), C.c_void_p, C.c_void_p,
                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "fm_profile_iterations": (C.c_int, [C.c_void_p, C.POINTER(LoadStep), C.c_int32,
+                                        C.POINTER(C.c_double)]),
     "fm_plan_total_iterations": (C.c_int64, [C.c_void_p]),
     "fm_plan_destroy": (None, [C.c_void_p]),
     "fm_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p,
@@ -226,10 +228,11 @@ class Plan:
 
     def set_material(self, mat_id, materials):
         torch = self.torch
-        ids = torch.as_tensor(np.ascontiguousarray(mat_id, dtype=np.int32).reshape(-1), device="cuda")
-        tab = material_table(self.prob)
-        check(lib().fm_set_material(self.handle, C.c_void_p(ids.data_ptr()), len(materials), tab),
-              "fm_set_material")
+        self._ids = torch.as_tensor(np.ascontiguousarray(mat_id, dtype=np.int32).reshape(-1),
+                                    device="cuda")
+        self._tab = material_table(self.prob)
+        check(lib().fm_set_material(self.handle, C.c_void_p(self._ids.data_ptr()), len(materials),
+                                    self._tab), "fm_set_material")
         torch.cuda.current_stream().synchronize()
 
     def output_buffers(self):
@@ -299,6 +302,24 @@ class Plan:
                                 C.byref(err), macro), "fm_residual")
         n1, n2, n3 = self.n
         return Dd.cpu().numpy().reshape(3, n3 + 1, n2 + 1, n1 + 1), err.value, np.array(macro[:])
+
+    KERNELS = ("stress", "div", "control", "gram", "alpha", "x_fwd", "y_fwd", "z_green",
+               "y_inv", "x_inv_update")
+
+    def profile(self, step=None, n_iter=10):
+        """Mean per-kernel duration (ms) of the iteration, from HIP events on the plan's stream."""
+        step = self.prob.steps[0] if step is None else step
+        ms = (C.c_double * 10)()
+        check(lib().fm_profile_iterations(self.handle, load_steps([step]), n_iter, ms),
+              "fm_profile_iterations")
+        return dict(zip(self.KERNELS, list(ms)))
+
+    def reset(self, sync=True):
+        """Zero the displacement and internal variables (same device-resident microstructure)."""
+        check(lib().fm_set_material(self.handle, C.c_void_p(self._ids.data_ptr()),
+                                    len(self.prob.materials), self._tab), "fm_set_material")
+        if sync:
+            self.torch.cuda.current_stream().synchronize()
 
     def total_iterations(self):
         return int(lib().fm_plan_total_iterations(self.handle))

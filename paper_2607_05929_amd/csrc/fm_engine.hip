@@ -88,11 +88,21 @@ void factor(int L, std::vector<int>& r) {
     while (L % p == 0) { r.push_back(p); L /= p; }
 }
 
-int choose_F(int L, int rbytes, int packed_cap) {
-  const size_t per = 2 * (size_t)(L + 4) * 2 * rbytes;
-  int F = (int)std::max<size_t>(1, 65536 / per);
-  F = std::min(F, packed_cap);
-  return std::max(F, 1);
+// FFTs per block: bounded by the register staging of the in-place stages
+// (F L <= PASS_MAXPTS) and by 16 (32 packed real columns = one 128-byte row
+// segment in FP32).
+int choose_F(int L, int rbytes, int cap) {
+  (void)rbytes;
+  int F = std::max(1, PASS_MAXPTS / std::max(L, 1));
+  return std::max(1, std::min(F, cap));
+}
+
+bool generic_radix(int L) {
+  std::vector<int> r;
+  factor(L, r);
+  for (int v : r)
+    if (v != 2 && v != 3 && v != 4 && v != 5 && v != 8) return true;
+  return false;
 }
 
 int make_geometry(const fm_plan_desc* d, Geometry& g) {
@@ -142,8 +152,8 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
     g.F[q][3] = g.F[q][1];
     g.F[q][2] = choose_F(g.L[q][2], g.rbytes, 16);
   }
-  g.ntile_s = (int)cdiv(g.Nv, 256);
-  g.ntile_d = (int)cdiv(g.Nn, 256);
+  g.ntile_s = (int)cdiv(g.Nv, SPACE_TILE);
+  g.ntile_d = (int)cdiv(g.Nn, SPACE_TILE);
   return 0;
 }
 
@@ -388,6 +398,7 @@ struct fm_plan {
 // A set of solves advanced together.
 struct Group {
   int prec = 0;
+  int plastic = 0;    // any solve with J2 / CP internal variables
   int ns = 0;
   hipStream_t stream = nullptr;
   SolveDev* S = nullptr;
@@ -553,6 +564,8 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   if (ns < 1) return fail(FM_E_INVALID_ARG, "empty group");
   G.prec = plans[0]->d.prec;
   G.ns = ns;
+  G.plastic = 0;
+  for (int i = 0; i < ns; ++i) G.plastic |= plans[i]->d.with_state ? 1 : 0;
   G.stream = stream;
   int64_t t[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int i = 0; i < ns; ++i) {
@@ -588,7 +601,7 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
         int64_t ntiles = pass == 0 || pass == 4 ? d.tiles_p0 : (int64_t)d.tiles_p0 * d.n_p1;
         const int wk = pass == 0 ? 2 : pass == 1 ? 3 : pass == 2 ? 4 : pass == 3 ? 5 : 6;
         for (int64_t ty = 0; ty < ntiles; ++ty) wl[wk].push_back(make_int2(di, (int)ty));
-        const size_t lds = 2 * (size_t)d.F * (d.L + 4) * 2 * p->g.rbytes;
+        const size_t lds = (generic_radix(d.L) ? 2 : 1) * (size_t)d.F * pencil_stride(d.L) * 2 * p->g.rbytes;
         G.lds[pass] = std::max(G.lds[pass], lds);
       }
   }
@@ -608,30 +621,46 @@ template <typename R>
 int set_lds_limits() {
   static bool done = false;
   if (done) return 0;
-  const int big = 160 * 1024;
-  HIPCHK(hipFuncSetAttribute((const void*)k_xfwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_xinv<R>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_strided<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_strided<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_strided<R, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  const int big = 160 * 1024 - 2048;   // leave room for static shared arrays
+  HIPCHK(hipFuncSetAttribute((const void*)k_pass<R, 0, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_pass<R, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_pass<R, 0, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_pass<R, 1, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_pass<R, 2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   done = true;
+  return 0;
+}
+
+// Kernel k (0..9) of the iteration sequence.
+template <typename R>
+int launch_one(const Group& G, int k) {
+  hipStream_t st = G.stream;
+  switch (k) {
+    case 0:
+      if (!G.nwl[0]) break;
+      if (G.plastic) hipLaunchKernelGGL((k_stress<R, 1>), dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
+      else hipLaunchKernelGGL((k_stress<R, 0>), dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
+      break;
+    case 1: if (G.nwl[1]) hipLaunchKernelGGL(k_div<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]); break;
+    case 2: hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
+    case 3: if (G.nwl[1]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]); break;
+    case 4: hipLaunchKernelGGL(k_alpha, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
+    case 5: if (G.nwl[2]) hipLaunchKernelGGL((k_pass<R, 0, 1>), dim3(G.nwl[2]), dim3(PASS_THREADS), G.lds[0], st, G.P, G.wl[2], G.S); break;
+    case 6: if (G.nwl[3]) hipLaunchKernelGGL((k_pass<R, 0, 0>), dim3(G.nwl[3]), dim3(PASS_THREADS), G.lds[1], st, G.P, G.wl[3], G.S); break;
+    case 7: if (G.nwl[4]) hipLaunchKernelGGL((k_pass<R, 2, 0>), dim3(G.nwl[4]), dim3(PASS_THREADS), G.lds[2], st, G.P, G.wl[4], G.S); break;
+    case 8: if (G.nwl[5]) hipLaunchKernelGGL((k_pass<R, 1, 0>), dim3(G.nwl[5]), dim3(PASS_THREADS), G.lds[3], st, G.P, G.wl[5], G.S); break;
+    default: if (G.nwl[6]) hipLaunchKernelGGL((k_pass<R, 1, 1>), dim3(G.nwl[6]), dim3(PASS_THREADS), G.lds[4], st, G.P, G.wl[6], G.S); break;
+  }
+  HIPCHK(hipGetLastError());
   return 0;
 }
 
 template <typename R>
 int launch_iteration(const Group& G) {
-  hipStream_t st = G.stream;
-  if (G.nwl[0]) hipLaunchKernelGGL(k_stress<R>, dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
-  if (G.nwl[1]) hipLaunchKernelGGL(k_div<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]);
-  hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids);
-  if (G.nwl[1]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]);
-  hipLaunchKernelGGL(k_alpha, dim3(G.ns), dim3(256), 0, st, G.S, G.ids);
-  if (G.nwl[2]) hipLaunchKernelGGL(k_xfwd<R>, dim3(G.nwl[2]), dim3(256), G.lds[0], st, G.P, G.wl[2], G.S);
-  if (G.nwl[3]) hipLaunchKernelGGL((k_strided<R, 0>), dim3(G.nwl[3]), dim3(256), G.lds[1], st, G.P, G.wl[3], G.S);
-  if (G.nwl[4]) hipLaunchKernelGGL((k_strided<R, 2>), dim3(G.nwl[4]), dim3(256), G.lds[2], st, G.P, G.wl[4], G.S);
-  if (G.nwl[5]) hipLaunchKernelGGL((k_strided<R, 1>), dim3(G.nwl[5]), dim3(256), G.lds[3], st, G.P, G.wl[5], G.S);
-  if (G.nwl[6]) hipLaunchKernelGGL(k_xinv<R>, dim3(G.nwl[6]), dim3(256), G.lds[4], st, G.P, G.wl[6], G.S);
-  HIPCHK(hipGetLastError());
+  for (int k = 0; k < FM_N_KERNELS; ++k) {
+    const int rc = launch_one<R>(G, k);
+    if (rc) return rc;
+  }
   return 0;
 }
 
@@ -646,7 +675,8 @@ int launch_iterations(const Group& G, int count) {
 template <typename R>
 int launch_commit_t(fm_plan* p) {
   const Group& G = *p->self;
-  hipLaunchKernelGGL(k_stress<R>, dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0], 1);
+  if (G.plastic) hipLaunchKernelGGL((k_stress<R, 1>), dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0], 1);
+  else hipLaunchKernelGGL((k_stress<R, 0>), dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0], 1);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -910,19 +940,9 @@ int fm_apply_green(fm_plan* p, const double* d_x, double* d_w) {
   }
   HIPCHK(hipMemsetAsync(p->ws + p->lay.uf, 0, 8 * n3, p->stream));
   const Group& G = *p->self;
-  hipStream_t st = p->stream;
-  if (p->d.prec == FM_FP64) {
-    hipLaunchKernelGGL(k_xfwd<double>, dim3(G.nwl[2]), dim3(256), G.lds[0], st, G.P, G.wl[2], G.S);
-    hipLaunchKernelGGL((k_strided<double, 0>), dim3(G.nwl[3]), dim3(256), G.lds[1], st, G.P, G.wl[3], G.S);
-    hipLaunchKernelGGL((k_strided<double, 2>), dim3(G.nwl[4]), dim3(256), G.lds[2], st, G.P, G.wl[4], G.S);
-    hipLaunchKernelGGL((k_strided<double, 1>), dim3(G.nwl[5]), dim3(256), G.lds[3], st, G.P, G.wl[5], G.S);
-    hipLaunchKernelGGL(k_xinv<double>, dim3(G.nwl[6]), dim3(256), G.lds[4], st, G.P, G.wl[6], G.S);
-  } else {
-    hipLaunchKernelGGL(k_xfwd<float>, dim3(G.nwl[2]), dim3(256), G.lds[0], st, G.P, G.wl[2], G.S);
-    hipLaunchKernelGGL((k_strided<float, 0>), dim3(G.nwl[3]), dim3(256), G.lds[1], st, G.P, G.wl[3], G.S);
-    hipLaunchKernelGGL((k_strided<float, 2>), dim3(G.nwl[4]), dim3(256), G.lds[2], st, G.P, G.wl[4], G.S);
-    hipLaunchKernelGGL((k_strided<float, 1>), dim3(G.nwl[5]), dim3(256), G.lds[3], st, G.P, G.wl[5], G.S);
-    hipLaunchKernelGGL(k_xinv<float>, dim3(G.nwl[6]), dim3(256), G.lds[4], st, G.P, G.wl[6], G.S);
+  for (int k = 5; k < FM_N_KERNELS; ++k) {
+    const int rc = p->d.prec == FM_FP64 ? launch_one<double>(G, k) : launch_one<float>(G, k);
+    if (rc) return rc;
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(d_w, p->ws + p->lay.uf, 8 * n3, hipMemcpyDeviceToDevice, p->stream));
@@ -941,12 +961,9 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
   HIPCHK(hipMemcpyAsync(p->ws + p->lay.uf, d_uf, 8 * n3, hipMemcpyDeviceToDevice, p->stream));
   const Group& G = *p->self;
   hipStream_t st = p->stream;
-  if (p->d.prec == FM_FP64) {
-    hipLaunchKernelGGL(k_stress<double>, dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
-    hipLaunchKernelGGL(k_div<double>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]);
-  } else {
-    hipLaunchKernelGGL(k_stress<float>, dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
-    hipLaunchKernelGGL(k_div<float>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]);
+  for (int k = 0; k < 2; ++k) {
+    rc = p->d.prec == FM_FP64 ? launch_one<double>(G, k) : launch_one<float>(G, k);
+    if (rc) return rc;
   }
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, G.S, G.ids);
   HIPCHK(hipGetLastError());
@@ -960,6 +977,53 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
   if (rc) return rc;
   if (err) *err = c.err;
   if (macro) for (int i = 0; i < 6; ++i) macro[i] = c.macro[i];
+  c.status = ST_IDLE;
+  HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FM_OK;
+}
+
+int fm_profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, double* ms) {
+  if (!p || !step || n_iter < 1 || !ms) return fail(FM_E_INVALID_ARG, "null argument");
+  if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called first");
+  int rc = begin_step(p, *step, 0, nullptr);
+  if (rc) return rc;
+  Ctrl c;
+  rc = read_ctrl(p, c);
+  if (rc) return rc;
+  c.tol = -1.0;                 // never converged
+  c.max_iter = 1 << 30;
+  HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, p->stream));
+  hipEvent_t ev[FM_N_KERNELS + 1];
+  for (int i = 0; i <= FM_N_KERNELS; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  for (int k = 0; k < FM_N_KERNELS; ++k) ms[k] = 0;
+  const Group& G = *p->self;
+  hipStream_t st = p->stream;
+  // all iterations are enqueued before the first wait, so the stream runs the
+  // kernels back to back and each interval is one kernel's execution
+  std::vector<hipEvent_t> evs((size_t)n_iter * (FM_N_KERNELS + 1));
+  for (auto& x : evs) HIPCHK(hipEventCreate(&x));
+  for (int it = 0; it < n_iter; ++it) {
+    hipEvent_t* e = &evs[(size_t)it * (FM_N_KERNELS + 1)];
+    HIPCHK(hipEventRecord(e[0], st));
+    for (int k = 0; k < FM_N_KERNELS; ++k) {
+      if (p->d.prec == FM_FP64) rc = launch_one<double>(G, k);
+      else rc = launch_one<float>(G, k);
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(e[k + 1], st));
+    }
+  }
+  HIPCHK(hipEventSynchronize(evs.back()));
+  for (int it = 0; it < n_iter; ++it) {
+    hipEvent_t* e = &evs[(size_t)it * (FM_N_KERNELS + 1)];
+    for (int k = 0; k < FM_N_KERNELS; ++k) {
+      float tms = 0;
+      HIPCHK(hipEventElapsedTime(&tms, e[k], e[k + 1]));
+      ms[k] += tms / n_iter;
+    }
+  }
+  for (auto& x : evs) HIPCHK(hipEventDestroy(x));
+  for (int i = 0; i <= FM_N_KERNELS; ++i) HIPCHK(hipEventDestroy(ev[i]));
   c.status = ST_IDLE;
   HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));

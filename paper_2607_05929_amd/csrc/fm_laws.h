@@ -182,6 +182,27 @@ __device__ void cp_update(const R* P, const R em[6], const R epn[6], R Gn, R dt,
   Gout = Gn + dG;
 }
 
+// Elastic laws only (isotropic, rotated anisotropic).
+template <typename R>
+__device__ __forceinline__ void law_elastic(int law, const R* __restrict__ P, const R eps[6], R sig[6],
+                                            const R st[7], R stn[7]) {
+  if (law == LAW_ISO) {
+    const R lam = P[0], mu = P[1];
+    const R tr = eps[0] + eps[1] + eps[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) sig[i] = 2 * mu * eps[i] + lam * tr;
+#pragma unroll
+    for (int i = 3; i < 6; ++i) sig[i] = 2 * mu * eps[i];
+  } else {
+    R em[6], sm[6];
+    to_mandel(eps, em);
+    mat6(P, em, sm);
+    from_mandel(sm, sig);
+  }
+#pragma unroll
+  for (int i = 0; i < 7; ++i) stn[i] = st[i];
+}
+
 template <typename R>
 __device__ __forceinline__ void law_eval(int law, const R* __restrict__ P, const R eps[6], R sig[6], const R st[7],
                                          R stn[7], R dt) {

@@ -21,6 +21,8 @@
 
 namespace fm {
 
+constexpr int SPACE_TILE = 1024;   // voxels / nodes per 256-thread block (4 per thread)
+
 __device__ __forceinline__ int vidx(int l, int q) {
   // Voigt index of the symmetric pair (l, q): xx yy zz yz xz xy
   return l == q ? l : 6 - l - q;
@@ -71,15 +73,17 @@ __device__ __forceinline__ bool node_kept(int kind, int n, int j) {
   }
 }
 
-// mode 0: iteration; mode 1: commit (state update + FP64 outputs)
-template <typename R>
+// mode 0: iteration; mode 1: commit (state update + FP64 outputs).
+// PL = 0 compiles the elastic laws only (no internal variables), PL = 1 all laws.
+template <typename R, int PL>
 __global__ void __launch_bounds__(256) k_stress(const SolveDev* __restrict__ S, const int2* __restrict__ work, int mode) {
   const int2 w = work[blockIdx.x];
   const SolveDev& s = S[w.x];
   const Ctrl* C = s.ctrl;
   if (mode == 0 && C->status != ST_RUNNING) return;
-  const int64_t v = (int64_t)w.y * 256 + threadIdx.x;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int sub = 0; sub < SPACE_TILE / 256; ++sub) {
+  const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
   if (v < s.Nv) {
     const int n0 = s.n[0], n1 = s.n[1];
     const int x = (int)(v % n0);
@@ -146,7 +150,7 @@ __global__ void __launch_bounds__(256) k_stress(const SolveDev* __restrict__ S, 
                   (R)(0.5 * (g[0][2] + g[2][0])), (R)(0.5 * (g[0][1] + g[1][0]))};
       R st[7], stn[7];
       R* state = (R*)s.state;
-      if (s.has_state) {
+      if (PL && s.has_state) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) st[k] = state[((int64_t)k * s.nppv + r) * s.Nv + v];
       } else {
@@ -154,7 +158,8 @@ __global__ void __launch_bounds__(256) k_stress(const SolveDev* __restrict__ S, 
         for (int k = 0; k < 7; ++k) st[k] = 0;
       }
       R sig[6];
-      law_eval<R>(law, P, eps, sig, st, stn, (R)C->dt);
+      if (PL) law_eval<R>(law, P, eps, sig, st, stn, (R)C->dt);
+      else law_elastic<R>(law, P, eps, sig, st, stn);
       if (mode == 0) {
         R* so = (R*)s.sig;
 #pragma unroll
@@ -168,7 +173,7 @@ __global__ void __launch_bounds__(256) k_stress(const SolveDev* __restrict__ S, 
         }
         acc[0] += wip * n2;
       } else {
-        if (s.has_state && (law == LAW_J2 || law == LAW_CP)) {
+        if (PL && s.has_state && (law == LAW_J2 || law == LAW_CP)) {
 #pragma unroll
           for (int k = 0; k < 7; ++k) state[((int64_t)k * s.nppv + r) * s.Nv + v] = stn[k];
         }
@@ -182,6 +187,7 @@ __global__ void __launch_bounds__(256) k_stress(const SolveDev* __restrict__ S, 
         }
       }
     }
+  }
   }
   if (mode == 0) {
     __shared__ double outp[7];
@@ -197,8 +203,9 @@ __global__ void __launch_bounds__(256) k_div(const SolveDev* __restrict__ S, con
   const SolveDev& s = S[w.x];
   const Ctrl* C = s.ctrl;
   if (C->status != ST_RUNNING) return;
-  const int64_t v = (int64_t)w.y * 256 + threadIdx.x;
   double acc[1] = {0};
+  for (int sub = 0; sub < SPACE_TILE / 256; ++sub) {
+  const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
   if (v < s.Nn) {
     const int N0 = s.N[0], N1 = s.N[1];
     const int J[3] = {(int)(v % N0), (int)((v / N0) % N1), (int)(v / ((int64_t)N0 * N1))};
@@ -256,6 +263,7 @@ __global__ void __launch_bounds__(256) k_div(const SolveDev* __restrict__ S, con
       Dout[q * s.Nn + v] = D;
     }
   }
+  }
   __shared__ double outp[1];
   block_sum<1>(acc, outp);
   __syncthreads();
@@ -268,11 +276,12 @@ __global__ void __launch_bounds__(256) k_gram(const SolveDev* __restrict__ S, co
   const SolveDev& s = S[w.x];
   const Ctrl* C = s.ctrl;
   if (C->status != ST_RUNNING || !C->aa_pending) return;
-  const int64_t v = (int64_t)w.y * 256 + threadIdx.x;
   double acc[NGRAM];
 #pragma unroll
   for (int i = 0; i < NGRAM; ++i) acc[i] = 0;
   const int k = C->win_n;
+  for (int sub = 0; sub < SPACE_TILE / 256; ++sub) {
+  const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
   if (v < s.Nn) {
     const int N0 = s.N[0], N1 = s.N[1];
     const int J[3] = {(int)(v % N0), (int)((v / N0) % N1), (int)(v / ((int64_t)N0 * N1))};
@@ -292,6 +301,7 @@ __global__ void __launch_bounds__(256) k_gram(const SolveDev* __restrict__ S, co
 #pragma unroll
         for (int b = a; b < MAX_DEPTH; ++b) acc[t++] += d[a] * d[b];
     }
+  }
   }
   __shared__ double outp[NGRAM];
   block_sum<NGRAM>(acc, outp);
