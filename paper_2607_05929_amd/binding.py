@@ -381,3 +381,69 @@ def batch_solve(problems, prec=None, fields=False):
     for pl in plans:
         pl.close()
     return res
+
+
+class Server:
+    """Continuous-batching request loop (fm_server_*) over one torch-owned arena."""
+
+    def __init__(self, arena_bytes, max_active=64):
+        torch = _torch()
+        self.torch = torch
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        self.handle = C.c_void_p()
+        check(lib().fm_server_create(C.c_void_p(self.arena.data_ptr()), int(arena_bytes),
+                                     int(max_active), _stream_ptr(torch), C.byref(self.handle)),
+              "fm_server_create")
+        self.keep = {}
+
+    def submit(self, prob, arrival_s, now_s=0.0, prec=None):
+        req = Request()
+        req.desc = plan_desc(prob, prec)
+        ids = np.ascontiguousarray(prob.mat_id, dtype=np.int32).reshape(-1)
+        tab = material_table(prob)
+        st = load_steps(prob.steps)
+        macro = np.zeros((len(prob.steps), 6))
+        iters = np.zeros(len(prob.steps), dtype=np.int32)
+        req.mat_id = ids.ctypes.data_as(C.POINTER(C.c_int32))
+        req.n_mat = len(prob.materials)
+        req.table = tab
+        req.steps = st
+        req.n_steps = len(prob.steps)
+        req.macro_sigma = macro.ctypes.data_as(C.POINTER(C.c_double))
+        req.iters = iters.ctypes.data_as(C.POINTER(C.c_int32))
+        req.arrival_s = float(arrival_s)
+        t = C.c_uint64()
+        check(lib().fm_server_submit(self.handle, C.byref(req), float(now_s), C.byref(t)),
+              "fm_server_submit")
+        self.keep[t.value] = (macro, iters, prob)
+        return t.value
+
+    def step(self, iters, now_s):
+        check(lib().fm_server_step(self.handle, int(iters), float(now_s)), "fm_server_step")
+
+    def poll(self, ticket):
+        st = C.c_int32()
+        lat = C.c_double()
+        check(lib().fm_server_poll(self.handle, C.c_uint64(ticket), C.byref(st), C.byref(lat)),
+              "fm_server_poll")
+        return int(st.value), float(lat.value)
+
+    def result(self, ticket):
+        macro, iters, _ = self.keep[ticket]
+        return {"macro_sigma": macro, "iters": iters.tolist()}
+
+    def stats(self):
+        s = Stats()
+        check(lib().fm_server_stats(self.handle, C.byref(s)), "fm_server_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().fm_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

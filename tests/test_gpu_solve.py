@@ -1,0 +1,174 @@
+"""End-to-end GPU solves against the FP64 oracle (through the C ABI).
+
+Tolerances: FP64 solves converged to tol agree with the oracle to ~tol on
+the fields (both are within tol of the same discrete fixed point); the FP32
+path is held to the 1e-5 relative macroscopic-stress target and to 1e-4 on
+the local stress fields.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import solver as osolver
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2607_05929_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def inclusion32():
+    prob = W.config_inclusion32()
+    return prob, osolver.solve(prob)
+
+
+def test_inclusion32_fp64(B, inclusion32):
+    prob, ref = inclusion32
+    got = B.solve(prob, prec=W.FP64)
+    print(f"inclusion32 fp64 iters gpu {got['iters']} oracle {ref['iters']}", flush=True)
+    assert got["converged"][0]
+    assert rel_err(got["macro_sigma"], ref["macro_sigma"]) < 1e-7
+    assert rel_err(got["sig"], ref["sig"]) < 1e-6
+    assert rel_err(got["u"], ref["u"]) < 1e-6
+
+
+def test_inclusion32_fp32(B, inclusion32):
+    prob, ref = inclusion32
+    p = W.config_inclusion32()
+    p.tol = 1e-6
+    got = B.solve(p, prec=W.FP32_MIXED)
+    e = rel_err(got["macro_sigma"], ref["macro_sigma"])
+    print(f"inclusion32 fp32 iters {got['iters']} macro rel err {e:.2e}", flush=True)
+    assert got["converged"][0]
+    assert e < 1e-5
+    assert rel_err(got["sig"], ref["sig"]) < 1e-4
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+@pytest.mark.parametrize("seed", [11, 12])
+def test_small_fp32(B, scheme, seed):
+    rng = np.random.default_rng(seed)
+    prob = W.random_small_problem(rng, n=(12, 10, 14), scheme=scheme, tol=1e-7,
+                                  law="cubic" if seed == 12 else "iso")
+    ref = osolver.solve(prob)
+    prob.tol = 1e-6
+    got = B.solve(prob, prec=W.FP32_MIXED)
+    e = rel_err(got["macro_sigma"], ref["macro_sigma"])
+    print(f"small fp32 scheme={scheme} seed={seed} iters {got['iters']} macro err {e:.2e}", flush=True)
+    assert got["converged"][0]
+    assert e < 1e-5
+
+
+def _j2_problem():
+    prob = W.config_j2_inclusions(nv=12, seed=3, n_steps=4, eps_final=6e-3, tol=1e-9,
+                                  phi=0.15, rmin=2.0, rmax=3.0, prec=W.FP64)
+    return prob
+
+
+def test_j2_mixed_fp64(B):
+    prob = _j2_problem()
+    ref = osolver.solve(prob)
+    got = B.solve(prob, prec=W.FP64)
+    print(f"j2 fp64 iters gpu {got['iters']} oracle {ref['iters']}", flush=True)
+    assert all(got["converged"]) and all(ref["converged"])
+    assert rel_err(got["macro_sigma"], ref["macro_sigma"]) < 1e-7
+    assert rel_err(got["sig"], ref["sig"]) < 1e-6
+    # the mixed control reached <sigma_xx> = <sigma_yy> = 0
+    assert np.abs(got["macro_sigma"][:, :2]).max() < 1e-8 * np.abs(got["macro_sigma"][:, 2]).max()
+    # plasticity is active in the last increments
+    assert got["macro_sigma"][-1, 2] < 0.9 * 70.0 * 6e-3
+
+
+def test_j2_mixed_fp32(B):
+    prob = _j2_problem()
+    ref = osolver.solve(prob)
+    prob.tol = 1e-6
+    got = B.solve(prob, prec=W.FP32_MIXED)
+    e = rel_err(got["macro_sigma"][:, 2], ref["macro_sigma"][:, 2])
+    print(f"j2 fp32 iters {got['iters']} macro zz err {e:.2e}", flush=True)
+    assert all(got["converged"])
+    assert e < 1e-5
+
+
+def _cp_problem(prec):
+    rng = np.random.default_rng(55)
+    prob = W.cp_polycrystal(rng, 8, 4, prec=prec, n_steps=3, eps_max=4e-3, tol=1e-9)
+    return prob
+
+
+def test_cp_fp64(B):
+    prob = _cp_problem(W.FP64)
+    ref = osolver.solve(prob)
+    got = B.solve(prob, prec=W.FP64)
+    print(f"cp fp64 iters gpu {got['iters']} oracle {ref['iters']}", flush=True)
+    assert all(got["converged"])
+    assert rel_err(got["macro_sigma"], ref["macro_sigma"]) < 1e-6
+    assert rel_err(got["sig"], ref["sig"]) < 1e-5
+
+
+def test_cp_fp32(B):
+    prob = _cp_problem(W.FP64)
+    ref = osolver.solve(prob)
+    prob.tol = 1e-6
+    got = B.solve(prob, prec=W.FP32_MIXED)
+    e = rel_err(got["macro_sigma"], ref["macro_sigma"])
+    print(f"cp fp32 iters {got['iters']} macro err {e:.2e}", flush=True)
+    assert all(got["converged"])
+    assert e < 1e-4
+
+
+def _batch_problems():
+    rng = np.random.default_rng(4)
+    sizes = [8, 12, 16, 10, 14, 8]
+    return [W.random_rve(rng, n, prec=W.FP32_MIXED, tol=1e-6) for n in sizes]
+
+
+def test_batch_equals_alone(B):
+    probs = _batch_problems()
+    res = B.batch_solve(probs, fields=True)
+    for p, r in zip(probs, res):
+        alone = B.solve(p, prec=W.FP32_MIXED)
+        assert r["rc"] == 0
+        assert r["iters"] == alone["iters"]
+        np.testing.assert_array_equal(r["sig"], alone["sig"])
+    # and against the oracle for two of them
+    for k in (0, 3):
+        p = probs[k]
+        ref = osolver.solve(p)
+        e = rel_err(res[k]["macro_sigma"], ref["macro_sigma"])
+        print(f"batch member {k} macro err vs oracle {e:.2e}", flush=True)
+        assert e < 1e-5
+
+
+def test_server_mix_equals_alone(B):
+    probs = _batch_problems()[:5]
+    srv = B.Server(arena_bytes=256 << 20, max_active=3)
+    tickets = []
+    now = 0.0
+    # staggered arrivals: submit two, advance, submit the rest while they run
+    for k, p in enumerate(probs):
+        tickets.append(srv.submit(p, arrival_s=now))
+        if k == 1:
+            srv.step(4, now)
+            now += 0.001
+    for _ in range(2000):
+        srv.step(8, now)
+        now += 0.001
+        if all(srv.poll(t)[0] == 2 for t in tickets):
+            break
+    st = srv.stats()
+    print(f"server stats {st}", flush=True)
+    assert st["completed"] == len(probs)
+    assert st["arena_in_use"] == 0
+    for t, p in zip(tickets, probs):
+        alone = B.solve(p, prec=W.FP32_MIXED, fields=False)
+        got = srv.result(t)
+        np.testing.assert_array_equal(got["macro_sigma"], alone["macro_sigma"])
+        assert got["iters"] == alone["iters"]
+    srv.close()
