@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run a 1 GiB device copy (torch) first: a plain copy kernel of known size "
+                         "used to scale the FETCH_SIZE / WRITE_SIZE counters, and its bandwidth")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
@@ -127,6 +130,22 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    copy_gbs = None
+    if args.calibrate:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t = time.time()
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        copy_gbs = 10 * 2 * (1 << 30) / (time.time() - t) / 1e9
+        log(f"calibration copy: 1 GiB read + 1 GiB write per launch, {copy_gbs:.0f} GB/s")
+        del a, b
 
     t = time.time()
     prob = W.config_polycrystal_bending(nv=args.size)
@@ -207,6 +226,7 @@ def main():
                      "iteration_ms": iter_ms, "iteration_bytes": iter_bytes,
                      "iteration_GBs": iter_bytes / (iter_ms * 1e-3) / 1e9,
                      "per_kernel_ms": prof},
+        "copy_GBs": copy_gbs,
         "fp64": fp64,
         "speedup_fp32_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "cpu_baseline": cpu,

@@ -23,6 +23,7 @@
 #include "../../include/fmsolve.h"
 #include "fm_pass.h"
 #include "fm_space.h"
+#include "fm_wave.h"
 
 using namespace fm;
 
@@ -57,7 +58,9 @@ struct Geometry {
   int cplx[3][3];    // element complex after forward pass on axis a
   int64_t s1[3], s2[3];   // reals of stage-1 / stage-2 buffers per component
   int L[3][3];
-  int F[3][5];       // FFTs per block per pass
+  int F[3][5];       // FFTs per block per pass (generic kernel)
+  int wE[3][5];      // wavefront kernel E = L / 64 per pass, 0 = generic kernel
+  int cols[3][5];    // columns (or rows) per block per pass
   int ntile_s, ntile_d;
 };
 
@@ -151,6 +154,25 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
     g.F[q][1] = choose_F(g.L[q][1], g.rbytes, 16);
     g.F[q][3] = g.F[q][1];
     g.F[q][2] = choose_F(g.L[q][2], g.rbytes, 16);
+    for (int pass = 0; pass < 5; ++pass) {
+      const int axis = pass == 0 || pass == 4 ? 0 : (pass == 2 ? 2 : 1);
+      const int L = g.L[q][axis];
+      const bool packed = axis == 0 ? true : !g.cplx[q][axis - 1];
+      const int E = L % 64 == 0 ? L / 64 : 0;
+      g.wE[q][pass] = (E && wave_E_ok(E)) ? E : 0;
+      if (g.wE[q][pass]) {
+        // wavefront kernel staging (bounded as in build_group) must fit the LDS
+        const int cols = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
+        const size_t rows = (size_t)g.n[axis] + 3;
+        const size_t bytes = rows * (cols + 1) * 2 * (size_t)g.rbytes;
+        if (bytes > 150 * 1024) g.wE[q][pass] = 0;
+      }
+      if (g.wE[q][pass]) g.cols[q][pass] = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
+      else g.cols[q][pass] = packed ? 2 * g.F[q][pass] : g.F[q][pass];
+      if (!g.wE[q][pass] && (generic_radix(L) ? 2 : 1) * (size_t)g.F[q][pass] * pencil_stride(L) * 2 * g.rbytes >
+                                160 * 1024 - 2048)
+        return fail(FM_E_UNSUPPORTED, "pencil too long for the LDS transform");
+    }
   }
   g.ntile_s = (int)cdiv(g.Nv, SPACE_TILE);
   g.ntile_d = (int)cdiv(g.Nn, SPACE_TILE);
@@ -175,13 +197,11 @@ void tiles_of(const Geometry& g, int64_t t[7]) {
   t[2] = t[3] = t[4] = t[5] = t[6] = 0;
   for (int q = 0; q < 3; ++q) {
     const int rows = g.N[1] * g.N[2];
-    t[2] += cdiv(rows, 2 * g.F[q][0]);
-    t[6] += cdiv(rows, 2 * g.F[q][4]);
-    const int coly = g.cplx[q][0] ? g.F[q][1] : 2 * g.F[q][1];
-    t[3] += cdiv(g.M[q][0], coly) * g.N[2];
-    t[5] += cdiv(g.M[q][0], coly) * g.N[2];
-    const int colz = g.cplx[q][1] ? g.F[q][2] : 2 * g.F[q][2];
-    t[4] += cdiv(g.M[q][0], colz) * g.M[q][1];
+    t[2] += cdiv(rows, g.cols[q][0]);
+    t[6] += cdiv(rows, g.cols[q][4]);
+    t[3] += cdiv(g.M[q][0], g.cols[q][1]) * g.N[2];
+    t[5] += cdiv(g.M[q][0], g.cols[q][3]) * g.N[2];
+    t[4] += cdiv(g.M[q][0], g.cols[q][2]) * g.M[q][1];
   }
 }
 
@@ -396,6 +416,13 @@ struct fm_plan {
 };
 
 // A set of solves advanced together.
+constexpr int NBUCKET = 10;   // pass kernel variants: generic + wavefront E = 1,2,3,4,5,6,8,12,16
+inline int bucket_of_E(int E) {
+  switch (E) { case 1: return 1; case 2: return 2; case 3: return 3; case 4: return 4; case 5: return 5;
+               case 6: return 6; case 8: return 7; case 12: return 8; case 16: return 9; default: return 0; }
+}
+constexpr int E_of_bucket[NBUCKET] = {0, 1, 2, 3, 4, 5, 6, 8, 12, 16};
+
 struct Group {
   int prec = 0;
   int plastic = 0;    // any solve with J2 / CP internal variables
@@ -403,10 +430,12 @@ struct Group {
   hipStream_t stream = nullptr;
   SolveDev* S = nullptr;
   PassDesc* P = nullptr;
-  int2* wl[7]{};
+  int2* wl[7]{};       // stress, div: whole lists; passes: concatenated buckets
   int64_t nwl[7]{};
+  int64_t boff[5][NBUCKET]{};   // start of each bucket inside wl[2 + pass]
+  int64_t bn[5][NBUCKET]{};     // items per bucket
+  size_t blds[5][NBUCKET]{};    // dynamic LDS per bucket
   int* ids = nullptr;
-  size_t lds[5]{};
 };
 
 namespace {
@@ -443,7 +472,7 @@ void fill_pass_descs(fm_plan* p) {
           d.cplx_in = 0; d.cplx_out = c1; d.packed = 1;
           d.len_in = g.N[0]; d.len_out = M0;
           d.n_p0 = g.N[1] * g.N[2];
-          d.cols = 2 * d.F;
+          d.cols = g.cols[q][pass];
           d.tiles_p0 = (int)cdiv(d.n_p0, d.cols);
           d.in_s1 = g.N[0]; d.out_s1 = M0;
           d.out = A;
@@ -454,7 +483,7 @@ void fill_pass_descs(fm_plan* p) {
           d.cplx_in = c1; d.cplx_out = 0; d.packed = 1;
           d.len_in = M0; d.len_out = g.N[0];
           d.n_p0 = g.N[1] * g.N[2];
-          d.cols = 2 * d.F;
+          d.cols = g.cols[q][pass];
           d.tiles_p0 = (int)cdiv(d.n_p0, d.cols);
           d.in_s1 = M0; d.out_s1 = g.N[0];
           d.in = A;
@@ -466,7 +495,7 @@ void fill_pass_descs(fm_plan* p) {
           d.cplx_in = c1; d.cplx_out = c2; d.packed = !c1;
           d.len_in = g.N[1]; d.len_out = M1;
           d.n_p0 = M0; d.n_p1 = g.N[2];
-          d.cols = d.packed ? 2 * d.F : d.F;
+          d.cols = g.cols[q][pass];
           d.tiles_p0 = (int)cdiv(M0, d.cols);
           d.in_sa = M0; d.in_s1 = (int64_t)M0 * g.N[1];
           d.out_sa = M0; d.out_s1 = (int64_t)M0 * M1;
@@ -476,7 +505,7 @@ void fill_pass_descs(fm_plan* p) {
           d.cplx_in = c2; d.cplx_out = c1; d.packed = !c1;
           d.len_in = M1; d.len_out = g.N[1];
           d.n_p0 = M0; d.n_p1 = g.N[2];
-          d.cols = d.packed ? 2 * d.F : d.F;
+          d.cols = g.cols[q][pass];
           d.tiles_p0 = (int)cdiv(M0, d.cols);
           d.in_sa = M0; d.in_s1 = (int64_t)M0 * M1;
           d.out_sa = M0; d.out_s1 = (int64_t)M0 * g.N[1];
@@ -486,7 +515,7 @@ void fill_pass_descs(fm_plan* p) {
           d.cplx_in = c2; d.cplx_out = c2; d.packed = !c2;
           d.len_in = g.N[2]; d.len_out = g.N[2];
           d.n_p0 = M0; d.n_p1 = M1;
-          d.cols = d.packed ? 2 * d.F : d.F;
+          d.cols = g.cols[q][pass];
           d.tiles_p0 = (int)cdiv(M0, d.cols);
           d.in_sa = d.out_sa = (int64_t)M0 * M1;
           d.in_s1 = d.out_s1 = M0;
@@ -583,9 +612,11 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   G.ids = (int*)(dev + o);
   std::vector<SolveDev> S(ns);
   std::vector<PassDesc> P(ns * 15);
-  std::vector<int2> wl[7];
+  std::vector<int2> wl[2];
+  std::vector<int2> pb[5][NBUCKET];
   std::vector<int> ids(ns);
-  for (int k = 0; k < 5; ++k) G.lds[k] = 0;
+  for (int k = 0; k < 5; ++k)
+    for (int b = 0; b < NBUCKET; ++b) G.blds[k][b] = 0;
   for (int i = 0; i < ns; ++i) {
     fm_plan* p = plans[i];
     S[i] = p->sd;
@@ -598,23 +629,62 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
         d.solve = i;
         const int di = i * 15 + q * 5 + pass;
         P[di] = d;
-        int64_t ntiles = pass == 0 || pass == 4 ? d.tiles_p0 : (int64_t)d.tiles_p0 * d.n_p1;
-        const int wk = pass == 0 ? 2 : pass == 1 ? 3 : pass == 2 ? 4 : pass == 3 ? 5 : 6;
-        for (int64_t ty = 0; ty < ntiles; ++ty) wl[wk].push_back(make_int2(di, (int)ty));
-        const size_t lds = (generic_radix(d.L) ? 2 : 1) * (size_t)d.F * pencil_stride(d.L) * 2 * p->g.rbytes;
-        G.lds[pass] = std::max(G.lds[pass], lds);
+        const int64_t ntiles = pass == 0 || pass == 4 ? d.tiles_p0 : (int64_t)d.tiles_p0 * d.n_p1;
+        const int pk = pass == 0 ? 0 : pass == 1 ? 1 : pass == 2 ? 2 : pass == 3 ? 3 : 4;   // launch order slot
+        const int E = p->g.wE[q][pass];
+        const int b = bucket_of_E(E);
+        for (int64_t ty = 0; ty < ntiles; ++ty) pb[pk][b].push_back(make_int2(di, (int)ty));
+        size_t lds;
+        const size_t R = p->g.rbytes;
+        if (E) {
+          // staging of phase A (input tile) and phase C (output tile), sized separately
+          const int mode = pass == 2 ? 2 : (pass == 3 || pass == 4) ? 1 : 0;
+          const bool half = d.packed && d.kind == K_DFT;
+          int j0, cnt;
+          raw_range(d.kind, d.n, j0, cnt);
+          const int rows_in = mode == 1 ? d.len_in : cnt;
+          const size_t es_in = d.cplx_in ? 2 * R : R;
+          const int M = half ? d.n / 2 + 1 : n_freq(d.kind, d.n);
+          const int rows_out = mode == 0 ? M : d.n + 1;
+          const size_t es_out = mode == 0 ? (d.cplx_out ? 2 * R : R) : (d.packed ? R : 2 * R);
+          lds = std::max((size_t)(rows_in + 2) * (d.cols + 1) * es_in, (size_t)(rows_out + 2) * (d.cols + 1) * es_out);
+        } else {
+          lds = (generic_radix(d.L) ? 2 : 1) * (size_t)d.F * pencil_stride(d.L) * 2 * R;
+        }
+        G.blds[pk][b] = std::max(G.blds[pk][b], lds);
       }
+  }
+  std::vector<int2> pl[5];
+  for (int k = 0; k < 5; ++k) {
+    int64_t off = 0;
+    for (int b = 0; b < NBUCKET; ++b) {
+      G.boff[k][b] = off;
+      G.bn[k][b] = (int64_t)pb[k][b].size();
+      pl[k].insert(pl[k].end(), pb[k][b].begin(), pb[k][b].end());
+      off += G.bn[k][b];
+    }
   }
   HIPCHK(hipMemcpyAsync(G.S, S.data(), sizeof(SolveDev) * ns, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(G.P, P.data(), sizeof(PassDesc) * ns * 15, hipMemcpyHostToDevice, stream));
   for (int k = 0; k < 7; ++k) {
-    G.nwl[k] = (int64_t)wl[k].size();
-    if (!wl[k].empty())
-      HIPCHK(hipMemcpyAsync(G.wl[k], wl[k].data(), sizeof(int2) * wl[k].size(), hipMemcpyHostToDevice, stream));
+    const std::vector<int2>& v = k < 2 ? wl[k] : pl[k - 2];
+    G.nwl[k] = (int64_t)v.size();
+    if (!v.empty())
+      HIPCHK(hipMemcpyAsync(G.wl[k], v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, stream));
   }
   HIPCHK(hipMemcpyAsync(G.ids, ids.data(), sizeof(int) * ns, hipMemcpyHostToDevice, stream));
   HIPCHK(hipStreamSynchronize(stream));
   return 0;
+}
+
+template <typename R, int E>
+hipError_t set_wave_lds(int big) {
+  hipError_t r;
+  if ((r = hipFuncSetAttribute((const void*)k_wave<R, 0, 1, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+  if ((r = hipFuncSetAttribute((const void*)k_wave<R, 1, 1, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+  if ((r = hipFuncSetAttribute((const void*)k_wave<R, 0, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+  if ((r = hipFuncSetAttribute((const void*)k_wave<R, 1, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+  return hipFuncSetAttribute((const void*)k_wave<R, 2, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
 template <typename R>
@@ -627,8 +697,54 @@ int set_lds_limits() {
   HIPCHK(hipFuncSetAttribute((const void*)k_pass<R, 0, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   HIPCHK(hipFuncSetAttribute((const void*)k_pass<R, 1, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   HIPCHK(hipFuncSetAttribute((const void*)k_pass<R, 2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK((set_wave_lds<R, 1>(big)));
+  HIPCHK((set_wave_lds<R, 2>(big)));
+  HIPCHK((set_wave_lds<R, 3>(big)));
+  HIPCHK((set_wave_lds<R, 4>(big)));
+  HIPCHK((set_wave_lds<R, 5>(big)));
+  HIPCHK((set_wave_lds<R, 6>(big)));
+  HIPCHK((set_wave_lds<R, 8>(big)));
+  HIPCHK((set_wave_lds<R, 12>(big)));
+  HIPCHK((set_wave_lds<R, 16>(big)));
   done = true;
   return 0;
+}
+
+template <typename R, int MODE, int XP>
+int launch_bucket(const Group& G, int pk, int b) {
+  const int2* wl = G.wl[2 + pk] + G.boff[pk][b];
+  const dim3 grid((unsigned)G.bn[pk][b]);
+  const size_t lds = G.blds[pk][b];
+  hipStream_t st = G.stream;
+  switch (E_of_bucket[b]) {
+    case 0: hipLaunchKernelGGL((k_pass<R, MODE, XP>), grid, dim3(PASS_THREADS), lds, st, G.P, wl, G.S); break;
+    case 1: hipLaunchKernelGGL((k_wave<R, MODE, XP, 1>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    case 2: hipLaunchKernelGGL((k_wave<R, MODE, XP, 2>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    case 3: hipLaunchKernelGGL((k_wave<R, MODE, XP, 3>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    case 4: hipLaunchKernelGGL((k_wave<R, MODE, XP, 4>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    case 5: hipLaunchKernelGGL((k_wave<R, MODE, XP, 5>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    case 6: hipLaunchKernelGGL((k_wave<R, MODE, XP, 6>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    case 8: hipLaunchKernelGGL((k_wave<R, MODE, XP, 8>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    case 12: hipLaunchKernelGGL((k_wave<R, MODE, XP, 12>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    default: hipLaunchKernelGGL((k_wave<R, MODE, XP, 16>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+  }
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess)
+    return fail(FM_E_HIP, std::string("pass launch (mode ") + std::to_string(MODE) + ", x " + std::to_string(XP) +
+                              ", E " + std::to_string(E_of_bucket[b]) + ", lds " + std::to_string(lds) +
+                              ", grid " + std::to_string(G.bn[pk][b]) + "): " + hipGetErrorString(err));
+  return 0;
+}
+
+template <typename R>
+int launch_pass(const Group& G, int pk, int b) {
+  switch (pk) {
+    case 0: return launch_bucket<R, 0, 1>(G, pk, b);
+    case 1: return launch_bucket<R, 0, 0>(G, pk, b);
+    case 2: return launch_bucket<R, 2, 0>(G, pk, b);
+    case 3: return launch_bucket<R, 1, 0>(G, pk, b);
+    default: return launch_bucket<R, 1, 1>(G, pk, b);
+  }
 }
 
 // Kernel k (0..9) of the iteration sequence.
@@ -645,11 +761,15 @@ int launch_one(const Group& G, int k) {
     case 2: hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
     case 3: if (G.nwl[1]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]); break;
     case 4: hipLaunchKernelGGL(k_alpha, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
-    case 5: if (G.nwl[2]) hipLaunchKernelGGL((k_pass<R, 0, 1>), dim3(G.nwl[2]), dim3(PASS_THREADS), G.lds[0], st, G.P, G.wl[2], G.S); break;
-    case 6: if (G.nwl[3]) hipLaunchKernelGGL((k_pass<R, 0, 0>), dim3(G.nwl[3]), dim3(PASS_THREADS), G.lds[1], st, G.P, G.wl[3], G.S); break;
-    case 7: if (G.nwl[4]) hipLaunchKernelGGL((k_pass<R, 2, 0>), dim3(G.nwl[4]), dim3(PASS_THREADS), G.lds[2], st, G.P, G.wl[4], G.S); break;
-    case 8: if (G.nwl[5]) hipLaunchKernelGGL((k_pass<R, 1, 0>), dim3(G.nwl[5]), dim3(PASS_THREADS), G.lds[3], st, G.P, G.wl[5], G.S); break;
-    default: if (G.nwl[6]) hipLaunchKernelGGL((k_pass<R, 1, 1>), dim3(G.nwl[6]), dim3(PASS_THREADS), G.lds[4], st, G.P, G.wl[6], G.S); break;
+    default: {
+      const int pk = k - 5;    // 0 x fwd, 1 y fwd, 2 z, 3 y inv, 4 x inv
+      for (int b = 0; b < NBUCKET; ++b)
+        if (G.bn[pk][b]) {
+          const int rc = launch_pass<R>(G, pk, b);
+          if (rc) return rc;
+        }
+      break;
+    }
   }
   HIPCHK(hipGetLastError());
   return 0;

@@ -45,10 +45,10 @@ __device__ __forceinline__ double green_factor(const PassDesc& d, int k0, int k1
   return 1.0 / den;
 }
 
-// LDS position of element e of a pencil: one pad slot every 32 complex
-// entries keeps the strided Stockham writes off a single bank group.
-__device__ __forceinline__ int PD(int e) { return e + (e >> 5); }
-__host__ __device__ inline int pencil_stride(int L) { return L + (L >> 5) + 4; }
+// LDS position of element e of a pencil (identity; a padded layout costs
+// more registers than its bank-conflict savings in this kernel).
+__device__ __forceinline__ int PD(int e) { return e; }
+__host__ __device__ inline int pencil_stride(int L) { return L + 4; }
 
 template <typename R>
 __device__ __forceinline__ cx<R> ldc(const void* base, int64_t idx) {

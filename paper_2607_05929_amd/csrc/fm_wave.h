@@ -1,0 +1,415 @@
+// Wavefront-per-pencil axis passes for pencil lengths L = 64 E (E in
+// {1, 2, 3, 4, 5, 6, 8, 12, 16}), the common case of the solver's grids.
+//
+// A block of 16 wavefronts owns a tile of 16 pencils (32 real columns packed
+// two per pencil, or 16 complex columns).  The tile is loaded with
+// coalesced 128-byte rows into an LDS staging array; each wavefront then
+// gathers its pencil's virtual extension (Table 1) straight into registers,
+// lane t holding positions t + 64 j (j < E), and transforms it with
+//   X[k1 + E k2] = sum_t W_L^{t k1} W_64^{t k2} sum_j x[t + 64 j] W_E^{j k1}:
+// an E-point DFT in registers, a twiddle, and a 64-point DFT across the
+// lanes (radix-2 butterflies through lane shuffles, then a bit-reversal
+// shuffle).  The Green operator of the fused z pass scales the spectrum in
+// registers.  Results go back through the staging array to coalesced stores.
+// No block barrier separates FFT stages; the staging array is the only LDS.
+#pragma once
+#include "fm_pass.h"
+
+namespace fm {
+
+constexpr int WAVE_PENCILS = 16;        // wavefronts (pencils) per block
+constexpr int WAVE_THREADS = 64 * WAVE_PENCILS;
+
+__host__ __device__ inline bool wave_E_ok(int E) {
+  return E == 1 || E == 2 || E == 3 || E == 4 || E == 5 || E == 6 || E == 8 || E == 12 || E == 16;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> shfl_xor_c(cx<R> v, int m) {
+  return mk<R>(__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64));
+}
+template <typename R>
+__device__ __forceinline__ cx<R> shfl_c(cx<R> v, int src) {
+  return mk<R>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
+}
+
+// 64-point DFT across the lanes of a wavefront: lane k ends with
+// sum_t v_t exp(sgn 2 pi i t k / 64).  Decimation in frequency (natural in,
+// bit-reversed out) followed by a bit-reversal shuffle.
+template <typename R>
+__device__ __forceinline__ cx<R> lane_dft64(cx<R> v, const cx<R>* W, int L, bool inv) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int h = 32; h >= 1; h >>= 1) {
+    const cx<R> pv = shfl_xor_c(v, h);
+    if (lane & h) {
+      const int r = lane & (h - 1);
+      v = sub(pv, v);
+      if (r) v = mul(v, twid(W, r * (L / (2 * h)), inv));
+    } else {
+      v = add(v, pv);
+    }
+  }
+  const int src = (int)(__brev((unsigned)lane) >> 26);
+  return shfl_c(v, src);
+}
+
+// In-register E-point DFT (natural order in and out).
+template <typename R, int E>
+__device__ __forceinline__ void dft_reg(cx<R> (&v)[E], const cx<R>* W, int L, bool inv) {
+  const R sgn = inv ? (R)1 : (R)-1;
+  if constexpr (E == 1) {
+    return;
+  } else if constexpr (E == 2) {
+    bfly2(v);
+  } else if constexpr (E == 3) {
+    bfly3(v, sgn);
+  } else if constexpr (E == 4) {
+    bfly4(v, sgn);
+  } else if constexpr (E == 5) {
+    bfly5(v, sgn);
+  } else if constexpr (E == 8) {
+    bfly8(v, sgn);
+  } else {
+    // E = A B: A-point DFTs over j = B ja + jb, twiddle W_E^{jb ka}, B-point DFTs
+    constexpr int A = (E == 6) ? 2 : (E == 12) ? 4 : 4;   // 6 = 2x3, 12 = 4x3, 16 = 4x4
+    constexpr int B = E / A;
+    cx<R> y[B][A];
+#pragma unroll
+    for (int jb = 0; jb < B; ++jb) {
+#pragma unroll
+      for (int ja = 0; ja < A; ++ja) y[jb][ja] = v[B * ja + jb];
+      if constexpr (A == 2) bfly2(y[jb]);
+      else bfly4(y[jb], sgn);
+#pragma unroll
+      for (int ka = 1; ka < A; ++ka)
+        if (jb) y[jb][ka] = mul(y[jb][ka], twid(W, (jb * ka) * (L / E), inv));
+    }
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) {
+      cx<R> z[B];
+#pragma unroll
+      for (int jb = 0; jb < B; ++jb) z[jb] = y[jb][ka];
+      if constexpr (B == 3) bfly3(z, sgn);
+      else bfly4(z, sgn);
+#pragma unroll
+      for (int kb = 0; kb < B; ++kb) v[ka + A * kb] = z[kb];
+    }
+  }
+}
+
+// Forward: lane t holds x[t + 64 j] in v[j]; on return lane k2 holds
+// X[k1 + E k2] in v[k1].  Inverse: the mirror image (unnormalised).
+template <typename R, int E>
+__device__ __forceinline__ void wave_fft(cx<R> (&v)[E], const cx<R>* W, int L, bool inv) {
+  const int t = threadIdx.x & 63;
+  if (!inv) {
+    dft_reg<R, E>(v, W, L, false);
+#pragma unroll
+    for (int k1 = 1; k1 < E; ++k1)
+      if (t) v[k1] = mul(v[k1], twid(W, t * k1, false));
+#pragma unroll
+    for (int k1 = 0; k1 < E; ++k1) v[k1] = lane_dft64(v[k1], W, L, false);
+  } else {
+#pragma unroll
+    for (int k1 = 0; k1 < E; ++k1) v[k1] = lane_dft64(v[k1], W, L, true);
+#pragma unroll
+    for (int k1 = 1; k1 < E; ++k1)
+      if (t) v[k1] = mul(v[k1], twid(W, t * k1, true));
+    dft_reg<R, E>(v, W, L, true);
+  }
+}
+
+// Value of the partner position L - m of register k1 (lane t holds
+// m = k1 + E t): register E - k1 of lane 63 - t, or register 0 of lane
+// 64 - t for k1 = 0.
+template <typename R, int E>
+__device__ __forceinline__ cx<R> mirror_val(const cx<R> (&v)[E], int k1) {
+  const int t = threadIdx.x & 63;
+  cx<R> out = mk<R>(0, 0);
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    // compile-time register selection: every lane takes the same register
+    const int want = (k1 == 0) ? 0 : E - k1;
+    if (q == want) out = shfl_c(v[q], k1 == 0 ? ((64 - t) & 63) : 63 - t);
+  }
+  return out;
+}
+
+// Staging element access.  Strided tiles: row e holds the columns
+// (pitch cols + 1); x tiles: row c holds the elements (pitch len + 1).
+template <int XP>
+__device__ __forceinline__ int sidx(int c, int e, int pitch) {
+  return XP ? c * pitch + e : e * pitch + c;
+}
+
+template <typename R, int MODE, int XP, int E>
+__global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restrict__ descs,
+                                                       const int2* __restrict__ work,
+                                                       const SolveDev* __restrict__ S) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ GreenCol<R> gcol[32];
+  const int2 wk = work[blockIdx.x];
+  const PassDesc& d = descs[wk.x];
+  const Ctrl* C = S[d.solve].ctrl;
+  if (C->status != ST_RUNNING) return;
+  constexpr int L = 64 * E;
+  const int n = d.n, kind = d.kind;
+  const int cols = d.cols;                      // 32 packed real or 16 complex
+  const bool packed = d.packed;
+  const bool half = packed && kind == K_DFT;
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  Tile tl;
+  if (XP) { tl.p0b = wk.y * cols; tl.p1 = 0; }
+  else { tl.p0b = (wk.y % d.tiles_p0) * cols; tl.p1 = wk.y / d.tiles_p0; }
+  tl.ncol = min(cols, d.n_p0 - tl.p0b);
+  const cx<R>* W = (const cx<R>*)d.tw;
+  R* sr = (R*)smem;            // staging, real elements (packed)
+  cx<R>* sc = (cx<R>*)smem;    // staging, complex elements
+
+  if (MODE == 2 && threadIdx.x < cols)
+    gcol[threadIdx.x] = green_col<R>(d, min(tl.p0b + (int)threadIdx.x, d.n_p0 - 1), tl.p1);
+
+  // ---------------- phase A: tile -> staging (coalesced) ----------------
+  int j0 = 0, cnt;
+  if (MODE == 1) cnt = d.len_in;
+  else raw_range(kind, n, j0, cnt);
+  const bool cin = d.cplx_in;
+  const int pitch = XP ? cnt + 1 : cols + 1;
+  {
+    const int nd = (XP && MODE == 0) ? C->n_d : 0;
+    R al[MAX_DEPTH];
+    const R* src[MAX_DEPTH];
+    if (XP && MODE == 0) {
+#pragma unroll
+      for (int q = 0; q < MAX_DEPTH; ++q) {
+        al[q] = q < nd ? (R)C->alpha[q] : (R)0;
+        src[q] = (const R*)d.ring + (int64_t)(q < nd ? C->slot_d[q] : 0) * d.ring_stride;
+      }
+    }
+    if (XP) {
+      for (int c = w; c < cols; c += WAVE_PENCILS)
+        for (int e = t; e < cnt; e += 64) {
+          const int si = sidx<1>(c, e, pitch);
+          if (c >= tl.ncol) { if (cin) sc[si] = mk<R>(0, 0); else sr[si] = 0; continue; }
+          if (MODE == 0) {
+            const int64_t o = addr<1>(tl, c, j0 + e, 0, d.in_s1);
+            R a = al[0] * src[0][o];
+#pragma unroll
+            for (int q = 1; q < MAX_DEPTH; ++q)
+              if (q < nd) a += al[q] * src[q][o];
+            sr[si] = a;
+          } else if (cin) {
+            sc[si] = ldc<R>(d.in, addr<1>(tl, c, j0 + e, 0, d.in_s1));
+          } else {
+            sr[si] = ((const R*)d.in)[addr<1>(tl, c, j0 + e, 0, d.in_s1)];
+          }
+        }
+    } else {
+      const int rows_per = 64 / cols;          // 2 (packed) or 4 (complex) rows per wavefront
+      const int c = t % cols;
+      for (int e = w * rows_per + t / cols; e < cnt; e += WAVE_PENCILS * rows_per) {
+        const int si = sidx<0>(c, e, pitch);
+        if (c >= tl.ncol) { if (cin) sc[si] = mk<R>(0, 0); else sr[si] = 0; continue; }
+        const int64_t o = addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1);
+        if (cin) sc[si] = ldc<R>(d.in, o);
+        else sr[si] = ((const R*)d.in)[o];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---------------- phase B: pencil -> registers, FFT ----------------
+  cx<R> v[E];
+  const int ca = packed ? 2 * w : w, cb = 2 * w + 1;   // columns of this pencil
+  if (MODE == 0 || MODE == 2) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int x = t + 64 * j;
+      int jn, sg;
+      ext_src(kind, n, x, jn, sg);
+      cx<R> z = mk<R>(0, 0);
+      if (sg) {
+        const int e = jn - j0;
+        if (packed) z = mk<R>(sr[sidx<XP>(ca, e, pitch)], sr[sidx<XP>(cb, e, pitch)]);
+        else z = sc[sidx<XP>(ca, e, pitch)];
+        if (sg < 0) z = scl(z, (R)-1);
+      }
+      v[j] = z;
+    }
+    wave_fft<R, E>(v, W, L, false);
+  } else {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int m = j + E * t;     // inverse input layout: lane t, register j <-> X[j + E t]
+      cx<R> z = mk<R>(0, 0);
+      if (half) {
+        // two Hermitian half spectra A (column ca) and B (column cb): Z = A + i B
+        const int km = m <= n / 2 ? m : n - m;
+        cx<R> A = sc[sidx<XP>(ca, km, pitch)], Bv = sc[sidx<XP>(cb, km, pitch)];
+        if (m > n / 2) { A = conj(A); Bv = conj(Bv); }
+        z = mk<R>(A.re - Bv.im, A.im + Bv.re);
+      } else {
+        int k;
+        R fr, fi;
+        if (spec_src<R>(kind, n, m, k, fr, fi)) {
+          const cx<R> g = packed ? mk<R>(sr[sidx<XP>(ca, k, pitch)], sr[sidx<XP>(cb, k, pitch)])
+                                 : sc[sidx<XP>(ca, k, pitch)];
+          z = mul(g, mk<R>(fr, fi));
+        }
+      }
+      v[j] = z;
+    }
+    wave_fft<R, E>(v, W, L, true);
+  }
+
+  if (MODE == 2) {
+    // Green operator on the spectrum held in registers (lane t, register k1:
+    // position m = k1 + E t); same structure-preserving scaling as the
+    // generic pass.
+    const double* zs2 = d.gs2[2];
+    const double* zc2 = d.gc2[2];
+    const uint8_t* zfl = d.gfl[2];
+    const bool okA = ca < tl.ncol, okB = packed ? cb < tl.ncol : false;
+    if (half) {
+      cx<R> nv[E];
+#pragma unroll
+      for (int k1 = 0; k1 < E; ++k1) {
+        const int m = k1 + E * t;
+        const cx<R> a = v[k1], b = conj(mirror_val<R, E>(v, k1));
+        const cx<R> A = scl(add(a, b), (R)0.5);
+        const cx<R> Bv = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
+        const int mk_ = m <= n / 2 ? m : n - m;
+        const R s2 = (R)zs2[mk_], c2 = (R)zc2[mk_];
+        const uint8_t fl = zfl[mk_];
+        const R fa = okA ? green_apply<R>(gcol[ca], d.scheme, s2, c2, fl) : (R)0;
+        const R fb = okB ? green_apply<R>(gcol[cb], d.scheme, s2, c2, fl) : (R)0;
+        nv[k1] = mk<R>(fa * A.re - fb * Bv.im, fa * A.im + fb * Bv.re);
+      }
+#pragma unroll
+      for (int k1 = 0; k1 < E; ++k1) v[k1] = nv[k1];
+    } else {
+#pragma unroll
+      for (int k1 = 0; k1 < E; ++k1) {
+        const int m = k1 + E * t;
+        int k;
+        R fr, fi;
+        if (!spec_src<R>(kind, n, m, k, fr, fi)) { v[k1] = mk<R>(0, 0); continue; }
+        const R s2 = (R)zs2[k], c2 = (R)zc2[k];
+        const uint8_t fl = zfl[k];
+        if (packed) {
+          const R fa = okA ? green_apply<R>(gcol[ca], d.scheme, s2, c2, fl) : (R)0;
+          const R fb = okB ? green_apply<R>(gcol[cb], d.scheme, s2, c2, fl) : (R)0;
+          v[k1] = (fi == (R)0) ? mk<R>(v[k1].re * fa, v[k1].im * fb) : mk<R>(v[k1].re * fb, v[k1].im * fa);
+        } else {
+          const R g = okA ? green_apply<R>(gcol[ca], d.scheme, s2, c2, fl) : (R)0;
+          v[k1] = scl(v[k1], g);
+        }
+      }
+    }
+    wave_fft<R, E>(v, W, L, true);
+  }
+
+  // ---------------- phase C: registers -> staging ----------------
+  __syncthreads();     // every wavefront has finished reading its inputs
+  int outcnt;
+  if (MODE == 0) {
+    const int M = half ? n / 2 + 1 : n_freq(kind, n);
+    outcnt = M;
+    const int opitch = XP ? M + 1 : cols + 1;
+#pragma unroll
+    for (int k1 = 0; k1 < E; ++k1) {
+      const int m = k1 + E * t;
+      // coefficient index carried by position m (inverse of the Table 1 map)
+      int k = -1;
+      R fr = 1, fi = 0;
+      switch (kind) {
+        case K_DFT: if (m < M) k = m; break;
+        case K_DCT1: if (m <= n) k = m; break;
+        case K_DST1: if (m >= 1 && m <= n - 1) { k = m - 1; fr = 0; fi = 1; } break;
+        case K_DCT3: if ((m & 1) && m < 2 * n) { k = (m - 1) >> 1; fr = (R)0.5; } break;
+        default: if ((m & 1) && m < 2 * n) { k = (m - 1) >> 1; fr = 0; fi = (R)0.5; } break;
+      }
+      cx<R> pm = mk<R>(0, 0);
+      if (half) pm = conj(mirror_val<R, E>(v, k1));    // shuffles: all lanes take part
+      if (k < 0) continue;
+      if (half) {
+        const cx<R> a = v[k1];
+        sc[sidx<XP>(ca, k, opitch)] = scl(add(a, pm), (R)0.5);
+        sc[sidx<XP>(cb, k, opitch)] = mk<R>((R)0.5 * (a.im - pm.im), (R)-0.5 * (a.re - pm.re));
+      } else {
+        const cx<R> g = mul(v[k1], mk<R>(fr, fi));
+        if (packed) { sr[sidx<XP>(ca, k, opitch)] = g.re; sr[sidx<XP>(cb, k, opitch)] = g.im; }
+        else sc[sidx<XP>(ca, k, opitch)] = g;
+      }
+    }
+  } else {
+    outcnt = n + 1;
+    const int opitch = XP ? n + 2 : cols + 1;
+    const R invL = (R)1 / (R)L;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int x = t + 64 * j;
+      // node j_node = x for x <= n; the periodic node n copies position 0
+      if (x > n) continue;
+      const int node = x;
+      const int srcx = node_src(kind, n, node);
+      cx<R> z = srcx < 0 ? mk<R>(0, 0) : scl(v[j], invL);
+      if (kind == K_DFT && x == n) z = mk<R>(0, 0);    // filled below from position 0
+      if (packed) { sr[sidx<XP>(ca, node, opitch)] = z.re; sr[sidx<XP>(cb, node, opitch)] = z.im; }
+      else sc[sidx<XP>(ca, node, opitch)] = z;
+      if (kind == K_DFT && x == 0) {
+        if (packed) { sr[sidx<XP>(ca, n, opitch)] = z.re; sr[sidx<XP>(cb, n, opitch)] = z.im; }
+        else sc[sidx<XP>(ca, n, opitch)] = z;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---------------- phase D: staging -> memory (coalesced) ----------------
+  const bool cout_ = (MODE == 0) ? d.cplx_out : !packed;
+  if (XP) {
+    const int opitch = outcnt + 1;
+    if (MODE == 0) {
+      for (int c = w; c < tl.ncol; c += WAVE_PENCILS)
+        for (int e = t; e < outcnt; e += 64) {
+          const int64_t o = addr<1>(tl, c, e, d.out_sa, d.out_s1);
+          if (cout_) stc<R>(d.out, o, sc[sidx<1>(c, e, opitch)]);
+          else ((R*)d.out)[o] = sr[sidx<1>(c, e, opitch)];
+        }
+    } else {
+      // x inverse: u^f += w - sum_k beta_k delta_k, new increment into the ring
+      const int nb = C->n_b;
+      R be[MAX_DEPTH];
+      const R* dsrc[MAX_DEPTH];
+#pragma unroll
+      for (int q = 0; q < MAX_DEPTH; ++q) {
+        be[q] = q < nb ? (R)C->beta[q] : (R)0;
+        dsrc[q] = (const R*)d.ring + (int64_t)(q < nb ? C->slot_b[q] : 0) * d.ring_stride;
+      }
+      R* dw = (R*)d.ring + (int64_t)C->slot_w * d.ring_stride;
+      for (int c = w; c < tl.ncol; c += WAVE_PENCILS)
+        for (int e = t; e < outcnt; e += 64) {
+          const int64_t o = (int64_t)(tl.p0b + c) * d.out_s1 + e;
+          R dl = sr[sidx<1>(c, e, opitch)];
+#pragma unroll
+          for (int q = 0; q < MAX_DEPTH; ++q)
+            if (q < nb) dl -= be[q] * dsrc[q][o];
+          dw[o] = dl;
+          d.uf[o] += (double)dl;
+        }
+    }
+  } else {
+    const int opitch = cols + 1;
+    const int rows_per = 64 / cols;
+    const int c = t % cols;
+    if (c < tl.ncol)
+      for (int e = w * rows_per + t / cols; e < outcnt; e += WAVE_PENCILS * rows_per) {
+        const int64_t o = addr<0>(tl, c, e, d.out_sa, d.out_s1);
+        if (cout_) stc<R>(d.out, o, sc[sidx<0>(c, e, opitch)]);
+        else ((R*)d.out)[o] = sr[sidx<0>(c, e, opitch)];
+      }
+  }
+}
+
+}  // namespace fm

@@ -6,6 +6,8 @@ FP32-mixed path stores fields in FP32 (unit round-off 6e-8), so single
 operator applications agree to 1e-5 relative and converged macroscopic
 stresses to the 1e-5 target of the FP32 mode.
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -52,6 +54,40 @@ def test_green_apply(B, prec, seed, n, scheme, green):
     gp.close()
     tol = 1e-11 if prec == W.FP64 else 2e-5
     print(f"green n={n} scheme={scheme} green={green} prec={prec} err={rel_err(got, ref):.2e}", flush=True)
+    assert rel_err(got, ref) < tol
+
+
+# Grids whose pencil lengths L = 64 E reach every wavefront-kernel variant
+# (E = 1, 2, 3, 4, 5, 6, 8, 12) on the x, y and z axes, for each transform kind.
+WAVE_SHAPES = [(256, 6, 5), (6, 256, 5), (5, 6, 256), (96, 160, 6), (192, 7, 128), (64, 32, 384)]
+BC_PATTERNS = {
+    "P": [W.P, W.P], "N": [W.N, W.N], "D": [W.D, W.D], "ND": [W.N, W.D], "DN": [W.D, W.N],
+}
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32_MIXED])
+@pytest.mark.parametrize("shape", WAVE_SHAPES)
+@pytest.mark.parametrize("pattern", ["P", "N", "D", "mix"])
+def test_green_apply_wave_lengths(B, prec, shape, pattern):
+    rng = np.random.default_rng(zlib.crc32(repr((shape, pattern)).encode()))
+    prob = W.random_small_problem(rng, n=shape, scheme=W.TETRA2 if pattern == "mix" else W.HEX1)
+    bc = np.zeros((3, 3, 2), dtype=np.int32)
+    names = list(BC_PATTERNS)
+    for q in range(3):
+        for i in range(3):
+            key = pattern if pattern != "mix" else names[(q + 2 * i) % len(names)]
+            bc[q, i] = BC_PATTERNS[key]
+    prob.bc = bc
+    pl = osolver.Plan(prob)
+    x = rng.standard_normal((3,) + tuple(v + 1 for v in shape))
+    for q in range(3):
+        fd.zero_dismissed(x[q], pl.exts[q])
+    ref = -pl.green_apply(x)
+    gp = B.Plan(prob, prec=prec)
+    got = xyz_nodes_from_zyx(gp.apply_green(zyx_nodes_from_xyz(x)))
+    gp.close()
+    tol = 1e-11 if prec == W.FP64 else 2e-5
+    print(f"green-wave shape={shape} pattern={pattern} prec={prec} err={rel_err(got, ref):.2e}", flush=True)
     assert rel_err(got, ref) < tol
 
 
