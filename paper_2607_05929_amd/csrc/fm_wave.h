@@ -33,25 +33,71 @@ __device__ __forceinline__ cx<R> shfl_c(cx<R> v, int src) {
   return mk<R>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
 }
 
-// 64-point DFT across the lanes of a wavefront: lane k ends with
-// sum_t v_t exp(sgn 2 pi i t k / 64).  Decimation in frequency (natural in,
-// bit-reversed out) followed by a bit-reversal shuffle.
+__device__ __forceinline__ int brev6(int x) { return (int)(__brev((unsigned)x) >> 26); }
+
+// Per-lane constants of the 64-point lane DFT.  Stage i pairs lanes that
+// differ in bit h = 32 >> i; sg[i] is +1 on the lane with the bit clear and
+// -1 on the lane with it set, s[i] is W_{2h}^{lane mod h} on the lane with the
+// bit set and 1 on the other (forward values; the inverse uses conjugates).
+// They depend on the lane only and are loaded once per pencil pass.
 template <typename R>
-__device__ __forceinline__ cx<R> lane_dft64(cx<R> v, const cx<R>* W, int L, bool inv) {
+struct LaneTw {
+  cx<R> s[5];
+  R sg[6];
+};
+
+template <typename R>
+__device__ __forceinline__ LaneTw<R> lane_twiddles(const cx<R>* W, int L) {
   const int lane = threadIdx.x & 63;
+  LaneTw<R> tw;
 #pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) {
-    const cx<R> pv = shfl_xor_c(v, h);
-    if (lane & h) {
-      const int r = lane & (h - 1);
-      v = sub(pv, v);
-      if (r) v = mul(v, twid(W, r * (L / (2 * h)), inv));
-    } else {
-      v = add(v, pv);
+  for (int i = 0; i < 6; ++i) {
+    const int h = 32 >> i;
+    tw.sg[i] = (lane & h) ? (R)-1 : (R)1;
+    if (i < 5) tw.s[i] = (lane & h) ? W[(lane & (h - 1)) * (L / (2 * h))] : mk<R>(1, 0);
+  }
+  return tw;
+}
+
+// Forward 64-point DFT across the lanes of every register, decimation in
+// frequency: lane t starts with x[t] and ends with X[brev6(t)].  Stages are
+// the outer loop so that the exchanges of all registers are in flight
+// together; the butterflies are branch free (sign and twiddle per lane).
+template <typename R, int E>
+__device__ __forceinline__ void lane_dif64(cx<R> (&v)[E], const LaneTw<R>& tw) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int h = 32 >> i;
+    cx<R> pv[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) pv[k] = shfl_xor_c(v[k], h);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      cx<R> z = mk<R>(fma(tw.sg[i], v[k].re, pv[k].re), fma(tw.sg[i], v[k].im, pv[k].im));
+      if (i < 5) z = mul(z, tw.s[i]);
+      v[k] = z;
     }
   }
-  const int src = (int)(__brev((unsigned)lane) >> 26);
-  return shfl_c(v, src);
+}
+
+// Inverse 64-point DFT across the lanes (unnormalised), decimation in time:
+// lane t starts with X[brev6(t)] and ends with x[t].
+template <typename R, int E>
+__device__ __forceinline__ void lane_dit64(cx<R> (&v)[E], const LaneTw<R>& tw) {
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    const int h = 32 >> i;
+    if (i < 5) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = mul(v[k], conj(tw.s[i]));
+    }
+    cx<R> pv[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) pv[k] = shfl_xor_c(v[k], h);
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      v[k] = mk<R>(fma(tw.sg[i], v[k].re, pv[k].re), fma(tw.sg[i], v[k].im, pv[k].im));
+  }
 }
 
 // In-register E-point DFT (natural order in and out).
@@ -98,40 +144,38 @@ __device__ __forceinline__ void dft_reg(cx<R> (&v)[E], const cx<R>* W, int L, bo
   }
 }
 
-// Forward: lane t holds x[t + 64 j] in v[j]; on return lane k2 holds
-// X[k1 + E k2] in v[k1].  Inverse: the mirror image (unnormalised).
+// Forward: lane t holds x[t + 64 j] in v[j]; on return lane t holds
+// X[k1 + E brev6(t)] in v[k1].  Inverse: the exact mirror image (input in
+// that bit-reversed layout, output x[t + 64 j] in v[j], unnormalised).
 template <typename R, int E>
-__device__ __forceinline__ void wave_fft(cx<R> (&v)[E], const cx<R>* W, int L, bool inv) {
+__device__ __forceinline__ void wave_fft(cx<R> (&v)[E], const cx<R>* W, const LaneTw<R>& tw, bool inv) {
+  constexpr int L = 64 * E;
   const int t = threadIdx.x & 63;
   if (!inv) {
     dft_reg<R, E>(v, W, L, false);
 #pragma unroll
-    for (int k1 = 1; k1 < E; ++k1)
-      if (t) v[k1] = mul(v[k1], twid(W, t * k1, false));
-#pragma unroll
-    for (int k1 = 0; k1 < E; ++k1) v[k1] = lane_dft64(v[k1], W, L, false);
+    for (int k1 = 1; k1 < E; ++k1) v[k1] = mul(v[k1], W[t * k1]);
+    lane_dif64<R, E>(v, tw);
   } else {
+    lane_dit64<R, E>(v, tw);
 #pragma unroll
-    for (int k1 = 0; k1 < E; ++k1) v[k1] = lane_dft64(v[k1], W, L, true);
-#pragma unroll
-    for (int k1 = 1; k1 < E; ++k1)
-      if (t) v[k1] = mul(v[k1], twid(W, t * k1, true));
+    for (int k1 = 1; k1 < E; ++k1) v[k1] = mul(v[k1], conj(W[t * k1]));
     dft_reg<R, E>(v, W, L, true);
   }
 }
 
-// Value of the partner position L - m of register k1 (lane t holds
-// m = k1 + E t): register E - k1 of lane 63 - t, or register 0 of lane
-// 64 - t for k1 = 0.
+// Value of the partner position L - m of register k1, where lane t holds
+// m = k1 + E b with b = brev6(t): register E - k1 of lane 63 - t, or, for
+// k1 = 0, register 0 of lane brev6((64 - b) & 63).
 template <typename R, int E>
-__device__ __forceinline__ cx<R> mirror_val(const cx<R> (&v)[E], int k1) {
+__device__ __forceinline__ cx<R> mirror_val(const cx<R> (&v)[E], int k1, int lane0) {
   const int t = threadIdx.x & 63;
   cx<R> out = mk<R>(0, 0);
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     // compile-time register selection: every lane takes the same register
     const int want = (k1 == 0) ? 0 : E - k1;
-    if (q == want) out = shfl_c(v[q], k1 == 0 ? ((64 - t) & 63) : 63 - t);
+    if (q == want) out = shfl_c(v[q], k1 == 0 ? lane0 : 63 - t);
   }
   return out;
 }
@@ -159,11 +203,14 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   const bool packed = d.packed;
   const bool half = packed && kind == K_DFT;
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int bt = brev6(t);                      // spectral lane order
+  const int mlane0 = brev6((64 - bt) & 63);     // lane of the partner of register 0
   Tile tl;
   if (XP) { tl.p0b = wk.y * cols; tl.p1 = 0; }
   else { tl.p0b = (wk.y % d.tiles_p0) * cols; tl.p1 = wk.y / d.tiles_p0; }
   tl.ncol = min(cols, d.n_p0 - tl.p0b);
   const cx<R>* W = (const cx<R>*)d.tw;
+  const LaneTw<R> ltw = lane_twiddles<R>(W, L);
   R* sr = (R*)smem;            // staging, real elements (packed)
   cx<R>* sc = (cx<R>*)smem;    // staging, complex elements
 
@@ -187,33 +234,85 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         src[q] = (const R*)d.ring + (int64_t)(q < nd ? C->slot_d[q] : 0) * d.ring_stride;
       }
     }
+    // Loads are issued in batches of U per thread before any is written to
+    // the staging array, so that U requests per lane are in flight at once.
+    constexpr int U = 8;
     if (XP) {
-      for (int c = w; c < cols; c += WAVE_PENCILS)
-        for (int e = t; e < cnt; e += 64) {
-          const int si = sidx<1>(c, e, pitch);
-          if (c >= tl.ncol) { if (cin) sc[si] = mk<R>(0, 0); else sr[si] = 0; continue; }
+      for (int c = w; c < cols; c += WAVE_PENCILS) {
+        const bool okc = c < tl.ncol;
+        for (int eb = t; eb < cnt; eb += U * 64) {
           if (MODE == 0) {
-            const int64_t o = addr<1>(tl, c, j0 + e, 0, d.in_s1);
-            R a = al[0] * src[0][o];
+            R tv[U];
 #pragma unroll
-            for (int q = 1; q < MAX_DEPTH; ++q)
-              if (q < nd) a += al[q] * src[q][o];
-            sr[si] = a;
+            for (int u = 0; u < U; ++u) {
+              const int e = eb + 64 * u;
+              tv[u] = 0;
+              if (okc && e < cnt) {
+                const int64_t o = addr<1>(tl, c, j0 + e, 0, d.in_s1);
+                R a = al[0] * src[0][o];
+#pragma unroll
+                for (int q = 1; q < MAX_DEPTH; ++q)
+                  if (q < nd) a += al[q] * src[q][o];
+                tv[u] = a;
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+              if (eb + 64 * u < cnt) sr[sidx<1>(c, eb + 64 * u, pitch)] = tv[u];
           } else if (cin) {
-            sc[si] = ldc<R>(d.in, addr<1>(tl, c, j0 + e, 0, d.in_s1));
+            cx<R> tv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int e = eb + 64 * u;
+              tv[u] = mk<R>(0, 0);
+              if (okc && e < cnt) tv[u] = ldc<R>(d.in, addr<1>(tl, c, j0 + e, 0, d.in_s1));
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+              if (eb + 64 * u < cnt) sc[sidx<1>(c, eb + 64 * u, pitch)] = tv[u];
           } else {
-            sr[si] = ((const R*)d.in)[addr<1>(tl, c, j0 + e, 0, d.in_s1)];
+            R tv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int e = eb + 64 * u;
+              tv[u] = 0;
+              if (okc && e < cnt) tv[u] = ((const R*)d.in)[addr<1>(tl, c, j0 + e, 0, d.in_s1)];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+              if (eb + 64 * u < cnt) sr[sidx<1>(c, eb + 64 * u, pitch)] = tv[u];
           }
         }
+      }
     } else {
       const int rows_per = 64 / cols;          // 2 (packed) or 4 (complex) rows per wavefront
       const int c = t % cols;
-      for (int e = w * rows_per + t / cols; e < cnt; e += WAVE_PENCILS * rows_per) {
-        const int si = sidx<0>(c, e, pitch);
-        if (c >= tl.ncol) { if (cin) sc[si] = mk<R>(0, 0); else sr[si] = 0; continue; }
-        const int64_t o = addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1);
-        if (cin) sc[si] = ldc<R>(d.in, o);
-        else sr[si] = ((const R*)d.in)[o];
+      const int step = WAVE_PENCILS * rows_per;
+      const bool okc = c < tl.ncol;
+      for (int eb = w * rows_per + t / cols; eb < cnt; eb += U * step) {
+        if (cin) {
+          cx<R> tv[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = eb + u * step;
+            tv[u] = mk<R>(0, 0);
+            if (okc && e < cnt) tv[u] = ldc<R>(d.in, addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1));
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (eb + u * step < cnt) sc[sidx<0>(c, eb + u * step, pitch)] = tv[u];
+        } else {
+          R tv[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = eb + u * step;
+            tv[u] = 0;
+            if (okc && e < cnt) tv[u] = ((const R*)d.in)[addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1)];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (eb + u * step < cnt) sr[sidx<0>(c, eb + u * step, pitch)] = tv[u];
+        }
       }
     }
   }
@@ -237,11 +336,11 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
       }
       v[j] = z;
     }
-    wave_fft<R, E>(v, W, L, false);
+    wave_fft<R, E>(v, W, ltw, false);
   } else {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int m = j + E * t;     // inverse input layout: lane t, register j <-> X[j + E t]
+      const int m = j + E * bt;    // inverse input layout: lane t, register j <-> X[j + E brev6(t)]
       cx<R> z = mk<R>(0, 0);
       if (half) {
         // two Hermitian half spectra A (column ca) and B (column cb): Z = A + i B
@@ -260,12 +359,12 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
       }
       v[j] = z;
     }
-    wave_fft<R, E>(v, W, L, true);
+    wave_fft<R, E>(v, W, ltw, true);
   }
 
   if (MODE == 2) {
     // Green operator on the spectrum held in registers (lane t, register k1:
-    // position m = k1 + E t); same structure-preserving scaling as the
+    // position m = k1 + E brev6(t)); same structure-preserving scaling as the
     // generic pass.
     const double* zs2 = d.gs2[2];
     const double* zc2 = d.gc2[2];
@@ -275,8 +374,8 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
       cx<R> nv[E];
 #pragma unroll
       for (int k1 = 0; k1 < E; ++k1) {
-        const int m = k1 + E * t;
-        const cx<R> a = v[k1], b = conj(mirror_val<R, E>(v, k1));
+        const int m = k1 + E * bt;
+        const cx<R> a = v[k1], b = conj(mirror_val<R, E>(v, k1, mlane0));
         const cx<R> A = scl(add(a, b), (R)0.5);
         const cx<R> Bv = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
         const int mk_ = m <= n / 2 ? m : n - m;
@@ -291,7 +390,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
     } else {
 #pragma unroll
       for (int k1 = 0; k1 < E; ++k1) {
-        const int m = k1 + E * t;
+        const int m = k1 + E * bt;
         int k;
         R fr, fi;
         if (!spec_src<R>(kind, n, m, k, fr, fi)) { v[k1] = mk<R>(0, 0); continue; }
@@ -307,7 +406,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         }
       }
     }
-    wave_fft<R, E>(v, W, L, true);
+    wave_fft<R, E>(v, W, ltw, true);
   }
 
   // ---------------- phase C: registers -> staging ----------------
@@ -319,7 +418,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
     const int opitch = XP ? M + 1 : cols + 1;
 #pragma unroll
     for (int k1 = 0; k1 < E; ++k1) {
-      const int m = k1 + E * t;
+      const int m = k1 + E * bt;
       // coefficient index carried by position m (inverse of the Table 1 map)
       int k = -1;
       R fr = 1, fi = 0;
@@ -331,7 +430,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         default: if ((m & 1) && m < 2 * n) { k = (m - 1) >> 1; fr = 0; fi = (R)0.5; } break;
       }
       cx<R> pm = mk<R>(0, 0);
-      if (half) pm = conj(mirror_val<R, E>(v, k1));    // shuffles: all lanes take part
+      if (half) pm = conj(mirror_val<R, E>(v, k1, mlane0));    // shuffles: all lanes take part
       if (k < 0) continue;
       if (half) {
         const cx<R> a = v[k1];
@@ -368,14 +467,29 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
 
   // ---------------- phase D: staging -> memory (coalesced) ----------------
   const bool cout_ = (MODE == 0) ? d.cplx_out : !packed;
+  constexpr int UD = 8;
   if (XP) {
     const int opitch = outcnt + 1;
     if (MODE == 0) {
       for (int c = w; c < tl.ncol; c += WAVE_PENCILS)
-        for (int e = t; e < outcnt; e += 64) {
-          const int64_t o = addr<1>(tl, c, e, d.out_sa, d.out_s1);
-          if (cout_) stc<R>(d.out, o, sc[sidx<1>(c, e, opitch)]);
-          else ((R*)d.out)[o] = sr[sidx<1>(c, e, opitch)];
+        for (int eb = t; eb < outcnt; eb += UD * 64) {
+          if (cout_) {
+            cx<R> tv[UD];
+#pragma unroll
+            for (int u = 0; u < UD; ++u)
+              if (eb + 64 * u < outcnt) tv[u] = sc[sidx<1>(c, eb + 64 * u, opitch)];
+#pragma unroll
+            for (int u = 0; u < UD; ++u)
+              if (eb + 64 * u < outcnt) stc<R>(d.out, addr<1>(tl, c, eb + 64 * u, d.out_sa, d.out_s1), tv[u]);
+          } else {
+            R tv[UD];
+#pragma unroll
+            for (int u = 0; u < UD; ++u)
+              if (eb + 64 * u < outcnt) tv[u] = sr[sidx<1>(c, eb + 64 * u, opitch)];
+#pragma unroll
+            for (int u = 0; u < UD; ++u)
+              if (eb + 64 * u < outcnt) ((R*)d.out)[addr<1>(tl, c, eb + 64 * u, d.out_sa, d.out_s1)] = tv[u];
+          }
         }
     } else {
       // x inverse: u^f += w - sum_k beta_k delta_k, new increment into the ring
@@ -388,26 +502,59 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         dsrc[q] = (const R*)d.ring + (int64_t)(q < nb ? C->slot_b[q] : 0) * d.ring_stride;
       }
       R* dw = (R*)d.ring + (int64_t)C->slot_w * d.ring_stride;
+      constexpr int UX = 4;
       for (int c = w; c < tl.ncol; c += WAVE_PENCILS)
-        for (int e = t; e < outcnt; e += 64) {
-          const int64_t o = (int64_t)(tl.p0b + c) * d.out_s1 + e;
-          R dl = sr[sidx<1>(c, e, opitch)];
+        for (int eb = t; eb < outcnt; eb += UX * 64) {
+          R dl[UX];
+          double uo[UX];
 #pragma unroll
-          for (int q = 0; q < MAX_DEPTH; ++q)
-            if (q < nb) dl -= be[q] * dsrc[q][o];
-          dw[o] = dl;
-          d.uf[o] += (double)dl;
+          for (int u = 0; u < UX; ++u) {
+            const int e = eb + 64 * u;
+            if (e < outcnt) {
+              const int64_t o = (int64_t)(tl.p0b + c) * d.out_s1 + e;
+              R a = sr[sidx<1>(c, e, opitch)];
+#pragma unroll
+              for (int q = 0; q < MAX_DEPTH; ++q)
+                if (q < nb) a -= be[q] * dsrc[q][o];
+              dl[u] = a;
+              uo[u] = d.uf[o];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < UX; ++u) {
+            const int e = eb + 64 * u;
+            if (e < outcnt) {
+              const int64_t o = (int64_t)(tl.p0b + c) * d.out_s1 + e;
+              dw[o] = dl[u];
+              d.uf[o] = uo[u] + (double)dl[u];
+            }
+          }
         }
     }
   } else {
     const int opitch = cols + 1;
     const int rows_per = 64 / cols;
+    const int step = WAVE_PENCILS * rows_per;
     const int c = t % cols;
     if (c < tl.ncol)
-      for (int e = w * rows_per + t / cols; e < outcnt; e += WAVE_PENCILS * rows_per) {
-        const int64_t o = addr<0>(tl, c, e, d.out_sa, d.out_s1);
-        if (cout_) stc<R>(d.out, o, sc[sidx<0>(c, e, opitch)]);
-        else ((R*)d.out)[o] = sr[sidx<0>(c, e, opitch)];
+      for (int eb = w * rows_per + t / cols; eb < outcnt; eb += UD * step) {
+        if (cout_) {
+          cx<R> tv[UD];
+#pragma unroll
+          for (int u = 0; u < UD; ++u)
+            if (eb + u * step < outcnt) tv[u] = sc[sidx<0>(c, eb + u * step, opitch)];
+#pragma unroll
+          for (int u = 0; u < UD; ++u)
+            if (eb + u * step < outcnt) stc<R>(d.out, addr<0>(tl, c, eb + u * step, d.out_sa, d.out_s1), tv[u]);
+        } else {
+          R tv[UD];
+#pragma unroll
+          for (int u = 0; u < UD; ++u)
+            if (eb + u * step < outcnt) tv[u] = sr[sidx<0>(c, eb + u * step, opitch)];
+#pragma unroll
+          for (int u = 0; u < UD; ++u)
+            if (eb + u * step < outcnt) ((R*)d.out)[addr<0>(tl, c, eb + u * step, d.out_sa, d.out_s1)] = tv[u];
+        }
       }
   }
 }
