@@ -108,7 +108,7 @@ typedef struct {
   double  quat[4];         /* unit quaternion (w, x, y, z); CUBIC and CP only */
 } fm_material;
 
-/* One load increment.  Prescribed displacement (Alg. 1, line 3)
+/* One load increment.  Prescribed displacement (set-up of Algorithm 1)
  *   u*_q(x) = c[q] + sum_l G[q][l] x_l + 1/2 sum_lm H[q][l][m] x_l x_m
  * at node positions x = (i h, j h, k h).  mixed_mask[c] != 0 makes Voigt
  * component c of sym(G) stress-controlled: it is moved after every iteration
@@ -203,7 +203,7 @@ int fm_batch_solve(fm_plan* const* plans, int32_t n_plans,
  *
  * fm_residual: for the fluctuation d_uf (device FP64, 3 x nodes) and the
  * load increment *step evaluated against the current internal variables,
- * writes D = div_d sigma at the nodes (Alg. 1 line 9; 0 at dismissed nodes)
+ * writes D = div_d sigma at the nodes (Algorithm 1; 0 at dismissed nodes)
  * to d_D (device FP64, 3 x nodes) and the equilibrium error and macroscopic
  * stress to the host (err: 1 double, macro: 6 doubles, either may be NULL).
  * Overwrites the plan's displacement. */
@@ -215,10 +215,10 @@ int fm_residual(fm_plan* plan, const fm_load_step* step, const double* d_uf, dou
  * iterations of *step with the convergence test disabled, recording HIP
  * events on the plan's stream around each of the FM_N_KERNELS launches, and
  * writes the mean duration in milliseconds per kernel to ms[FM_N_KERNELS]
- * (order: stress, div, control, gram, alpha, x-forward, y-forward,
+ * (order: stress+divergence, control, gram, alpha, x-forward, y-forward,
  * z-forward+Green+inverse, y-inverse, x-inverse+update).  Overwrites the
  * plan's displacement. */
-#define FM_N_KERNELS 10
+#define FM_N_KERNELS 9
 int fm_profile_iterations(fm_plan* plan, const fm_load_step* step, int32_t n_iter, double* ms);
 
 /* Iterations performed by the last fm_solve / fm_batch_solve of this plan. */

@@ -1,17 +1,17 @@
 """Algorithm 1 (algFFT) of the paper, written out step by step in FP64.
 
-For every load increment: update u* (Alg. line 3) and its discrete gradient
-(line 4; D* = 0, no applied tractions), predict u^f from the previous
-increment (line 5), then iterate:
+For every load increment (the set-up steps of Algorithm 1): update u* and
+its discrete gradient (D* = 0, no applied tractions) and predict u^f from the
+previous increment; then iterate (the loop of Algorithm 1):
 
-  * strain at the integration points, grad_d u = grad_d u^f + grad_d u*  (l.7)
-  * stress from the behaviour law                                         (l.8)
-  * D = div_d P + D*                                                      (l.9)
-  * equilibrium error, Eq. equilibrium_condition                          (l.10)
-  * stop if below the tolerance                                           (l.11-16)
-  * p = div_d(R0 : grad_d u^f) - D                                        (l.17)
-  * Anderson acceleration on p                                            (l.18)
-  * DTs of the accelerated p, Green operator, inverse DTs -> u^f          (l.19-21)
+  * strain at the integration points, grad_d u = grad_d u^f + grad_d u*
+  * stress from the behaviour law
+  * D = div_d P + D*
+  * equilibrium error, Eq. equilibrium_condition
+  * stop if below the tolerance
+  * p = div_d(R0 : grad_d u^f) - D
+  * Anderson acceleration on p
+  * DTs of the accelerated p, Green operator, inverse DTs -> u^f
 
 Readings where the paper is silent or garbled (listed in the design doc):
   * error  = h sqrt( sum_kept |D|^2 / sum_ip w_ip |sigma|_F^2 ), w_ip = 1/n_ppv

@@ -303,13 +303,13 @@ class Plan:
         n1, n2, n3 = self.n
         return Dd.cpu().numpy().reshape(3, n3 + 1, n2 + 1, n1 + 1), err.value, np.array(macro[:])
 
-    KERNELS = ("stress", "div", "control", "gram", "alpha", "x_fwd", "y_fwd", "z_green",
+    KERNELS = ("stress_div", "control", "gram", "alpha", "x_fwd", "y_fwd", "z_green",
                "y_inv", "x_inv_update")
 
     def profile(self, step=None, n_iter=10):
         """Mean per-kernel duration (ms) of the iteration, from HIP events on the plan's stream."""
         step = self.prob.steps[0] if step is None else step
-        ms = (C.c_double * 10)()
+        ms = (C.c_double * 9)()
         check(lib().fm_profile_iterations(self.handle, load_steps([step]), n_iter, ms),
               "fm_profile_iterations")
         return dict(zip(self.KERNELS, list(ms)))

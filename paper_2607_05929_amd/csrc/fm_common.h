@@ -17,6 +17,17 @@ enum Kind : int { K_DFT = 0, K_DCT1 = 1, K_DST1 = 2, K_DCT3 = 3, K_DST3 = 4 };
 
 enum Status : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 2, ST_IDLE = 3 };
 
+// Global-memory views of pointers read from descriptors.  A pointer loaded
+// from memory is generic to the compiler, which then emits flat memory
+// instructions; those also count against the LDS counter, so every wait on
+// one waits on the other.  Casting to the global address space gives global
+// loads and stores.
+#define FM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const FM_GLOBAL T* gconst(const T* p) { return (const FM_GLOBAL T*)p; }
+template <typename T>
+__device__ __forceinline__ FM_GLOBAL T* gmut(T* p) { return (FM_GLOBAL T*)p; }
+
 constexpr int MAX_DEPTH = 4;
 constexpr int MAX_RADICES = 12;
 constexpr int MT_STRIDE = 160;      // reals per material table entry
@@ -70,17 +81,19 @@ struct SolveDev {
   double* uf;             // 3*Nn (FP64 always)
   void* Dring;            // depth * 3 * Nn reals
   void* dring;            // depth * 3 * Nn reals
-  void* sig;              // 6 * nppv * Nv reals
   const uint16_t* mat;    // Nv
   const void* mtab;       // material table, MT_STRIDE reals per entry
   const int32_t* mlaw;    // law per material
   void* state;            // 7 * nppv * Nv reals (or null)
   Ctrl* ctrl;
   LogEntry* log;
-  double* part_s;         // ntile_s * NPART_S
+  double* part_s;         // ntile_s * NPART_S (stress-divergence tiles)
   double* part_d;         // ntile_d
   double* part_g;         // ntile_d * NGRAM
   int32_t ntile_s, ntile_d;
+  int32_t sd_nt[3];       // stress-divergence tiles per axis
+  int32_t wrap[3];        // axis periodic for some component
+  int32_t mixed_wrap;     // some axis periodic for some components only
   double* out_u;
   double* out_eps;
   double* out_sig;

@@ -3,7 +3,7 @@
 // A plan carves every buffer of one solve out of the caller's workspace;
 // a group (one plan, a batch, or the server's active set) owns the device
 // arrays that let a single kernel launch cover the tiles of all its solves.
-// The iteration sequence (Alg. 1, lines 7-21) is ten launches; all decisions
+// The iteration loop of Algorithm 1 is nine launches; all decisions
 // (convergence, Anderson schedule and weights, mixed loading) are taken on
 // the device, so the host enqueues iterations in chunks and only reads a few
 // status words between chunks.
@@ -61,7 +61,11 @@ struct Geometry {
   int F[3][5];       // FFTs per block per pass (generic kernel)
   int wE[3][5];      // wavefront kernel E = L / 64 per pass, 0 = generic kernel
   int cols[3][5];    // columns (or rows) per block per pass
-  int ntile_s, ntile_d;
+  int wrap[3];       // axis periodic for some component (halo voxels take the periodic image)
+  int sd_nt[3];      // fused stress-divergence tiles per axis
+  int ntile_s;       // fused stress-divergence tiles
+  int ntile_v;       // voxel tiles (commit)
+  int ntile_d;       // node tiles (Gram matrix)
 };
 
 int kind_of(int left, int right, int* out) {
@@ -174,26 +178,38 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
         return fail(FM_E_UNSUPPORTED, "pencil too long for the LDS transform");
     }
   }
-  g.ntile_s = (int)cdiv(g.Nv, SPACE_TILE);
+  for (int i = 0; i < 3; ++i) {
+    g.wrap[i] = 0;
+    for (int q = 0; q < 3; ++q) g.wrap[i] |= g.kinds[q][i] == K_DFT ? 1 : 0;
+  }
+  g.sd_nt[0] = (int)cdiv(g.N[0], SD_TX);
+  g.sd_nt[1] = (int)cdiv(g.N[1], SD_TY);
+  g.sd_nt[2] = (int)cdiv(g.N[2], SD_ZC);
+  g.ntile_s = g.sd_nt[0] * g.sd_nt[1] * g.sd_nt[2];
+  g.ntile_v = (int)cdiv(g.Nv, SPACE_TILE);
   g.ntile_d = (int)cdiv(g.Nn, SPACE_TILE);
   return 0;
 }
 
 // Layout of a plan workspace: offsets of every buffer.
 struct Layout {
-  size_t ctrl, log, uf, Dring, dring, sig, specA, specB, mat, mlaw, mtab, state, part_s, part_d, part_g,
+  size_t ctrl, log, uf, Dring, dring, specA, specB, mat, mlaw, mtab, state, part_s, part_d, part_g,
       tw, gtab, group, total;
   size_t tw_off[3][3];
   size_t g_off[3][3];   // green tables per comp, axis: s2 (M doubles), c2 (M doubles), flags (M bytes)
   size_t group_bytes;
 };
 
-size_t group_bytes_for(int nsolves, int64_t tiles_total[7]);
+// Work lists of a group: 0 voxel tiles (commit), 1 node tiles (Gram),
+// 2..6 the axis passes (x fwd, y fwd, z, y inv, x inv), 7 stress-divergence.
+constexpr int NWL = 8;
 
-void tiles_of(const Geometry& g, int64_t t[7]) {
-  // stress, div, xfwd, yfwd, z, yinv, xinv
-  t[0] = g.ntile_s;
+size_t group_bytes_for(int nsolves, int64_t tiles_total[NWL]);
+
+void tiles_of(const Geometry& g, int64_t t[NWL]) {
+  t[0] = g.ntile_v;
   t[1] = g.ntile_d;
+  t[7] = g.ntile_s;
   t[2] = t[3] = t[4] = t[5] = t[6] = 0;
   for (int q = 0; q < 3; ++q) {
     const int rows = g.N[1] * g.N[2];
@@ -205,11 +221,11 @@ void tiles_of(const Geometry& g, int64_t t[7]) {
   }
 }
 
-size_t group_bytes_for(int nsolves, int64_t tiles_total[7]) {
+size_t group_bytes_for(int nsolves, int64_t tiles_total[NWL]) {
   size_t b = 0;
   b += align_up(sizeof(SolveDev) * nsolves);
   b += align_up(sizeof(PassDesc) * nsolves * 15);
-  for (int i = 0; i < 7; ++i) b += align_up(sizeof(int2) * std::max<int64_t>(1, tiles_total[i]));
+  for (int i = 0; i < NWL; ++i) b += align_up(sizeof(int2) * std::max<int64_t>(1, tiles_total[i]));
   b += align_up(sizeof(int) * nsolves);
   return b;
 }
@@ -223,7 +239,6 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
   L.uf = take(8 * 3 * (size_t)g.Nn);
   L.Dring = take(R * g.depth * 3 * (size_t)g.Nn);
   L.dring = take(R * g.depth * 3 * (size_t)g.Nn);
-  L.sig = take(R * 6 * g.nppv * (size_t)g.Nv);
   L.specA = take(R * (size_t)(g.s1[0] + g.s1[1] + g.s1[2]));
   L.specB = take(R * (size_t)(g.s2[0] + g.s2[1] + g.s2[2]));
   L.mat = take(2 * (size_t)g.Nv);
@@ -237,7 +252,7 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
     for (int a = 0; a < 3; ++a) L.tw_off[q][a] = take(2 * R * (size_t)g.L[q][a]);
   for (int q = 0; q < 3; ++q)
     for (int a = 0; a < 3; ++a) L.g_off[q][a] = take(17 * (size_t)g.M[q][a]);
-  int64_t t[7];
+  int64_t t[NWL];
   tiles_of(g, t);
   L.group_bytes = group_bytes_for(1, t);
   L.group = take(L.group_bytes);
@@ -430,8 +445,8 @@ struct Group {
   hipStream_t stream = nullptr;
   SolveDev* S = nullptr;
   PassDesc* P = nullptr;
-  int2* wl[7]{};       // stress, div: whole lists; passes: concatenated buckets
-  int64_t nwl[7]{};
+  int2* wl[NWL]{};     // voxel, node, stress-divergence: whole lists; passes: concatenated buckets
+  int64_t nwl[NWL]{};
   int64_t boff[5][NBUCKET]{};   // start of each bucket inside wl[2 + pass]
   int64_t bn[5][NBUCKET]{};     // items per bucket
   size_t blds[5][NBUCKET]{};    // dynamic LDS per bucket
@@ -596,23 +611,23 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   G.plastic = 0;
   for (int i = 0; i < ns; ++i) G.plastic |= plans[i]->d.with_state ? 1 : 0;
   G.stream = stream;
-  int64_t t[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t t[NWL] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int i = 0; i < ns; ++i) {
     if (plans[i]->d.prec != G.prec) return fail(FM_E_INVALID_ARG, "a batch must share one precision");
-    int64_t ti[7];
+    int64_t ti[NWL];
     tiles_of(plans[i]->g, ti);
-    for (int k = 0; k < 7; ++k) t[k] += ti[k];
+    for (int k = 0; k < NWL; ++k) t[k] += ti[k];
   }
   const size_t need = group_bytes_for(ns, t);
   if (need > bytes) return fail(FM_E_WORKSPACE, "group workspace too small");
   size_t o = 0;
   G.S = (SolveDev*)(dev + o); o += align_up(sizeof(SolveDev) * ns);
   G.P = (PassDesc*)(dev + o); o += align_up(sizeof(PassDesc) * ns * 15);
-  for (int k = 0; k < 7; ++k) { G.wl[k] = (int2*)(dev + o); o += align_up(sizeof(int2) * std::max<int64_t>(1, t[k])); }
+  for (int k = 0; k < NWL; ++k) { G.wl[k] = (int2*)(dev + o); o += align_up(sizeof(int2) * std::max<int64_t>(1, t[k])); }
   G.ids = (int*)(dev + o);
   std::vector<SolveDev> S(ns);
   std::vector<PassDesc> P(ns * 15);
-  std::vector<int2> wl[2];
+  std::vector<int2> wl[3];
   std::vector<int2> pb[5][NBUCKET];
   std::vector<int> ids(ns);
   for (int k = 0; k < 5; ++k)
@@ -621,8 +636,9 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
     fm_plan* p = plans[i];
     S[i] = p->sd;
     ids[i] = i;
-    for (int ty = 0; ty < p->g.ntile_s; ++ty) wl[0].push_back(make_int2(i, ty));
+    for (int ty = 0; ty < p->g.ntile_v; ++ty) wl[0].push_back(make_int2(i, ty));
     for (int ty = 0; ty < p->g.ntile_d; ++ty) wl[1].push_back(make_int2(i, ty));
+    for (int ty = 0; ty < p->g.ntile_s; ++ty) wl[2].push_back(make_int2(i, ty));
     for (int q = 0; q < 3; ++q)
       for (int pass = 0; pass < 5; ++pass) {
         PassDesc d = p->pd[q][pass];
@@ -666,8 +682,8 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   }
   HIPCHK(hipMemcpyAsync(G.S, S.data(), sizeof(SolveDev) * ns, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(G.P, P.data(), sizeof(PassDesc) * ns * 15, hipMemcpyHostToDevice, stream));
-  for (int k = 0; k < 7; ++k) {
-    const std::vector<int2>& v = k < 2 ? wl[k] : pl[k - 2];
+  for (int k = 0; k < NWL; ++k) {
+    const std::vector<int2>& v = k < 2 ? wl[k] : (k < 7 ? pl[k - 2] : wl[2]);
     G.nwl[k] = (int64_t)v.size();
     if (!v.empty())
       HIPCHK(hipMemcpyAsync(G.wl[k], v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, stream));
@@ -706,6 +722,10 @@ int set_lds_limits() {
   HIPCHK((set_wave_lds<R, 8>(big)));
   HIPCHK((set_wave_lds<R, 12>(big)));
   HIPCHK((set_wave_lds<R, 16>(big)));
+  HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sdiv_lds_bytes(sizeof(R))));
+  HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sdiv_lds_bytes(sizeof(R))));
   done = true;
   return 0;
 }
@@ -753,16 +773,17 @@ int launch_one(const Group& G, int k) {
   hipStream_t st = G.stream;
   switch (k) {
     case 0:
-      if (!G.nwl[0]) break;
-      if (G.plastic) hipLaunchKernelGGL((k_stress<R, 1>), dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
-      else hipLaunchKernelGGL((k_stress<R, 0>), dim3(G.nwl[0]), dim3(256), 0, st, G.S, G.wl[0], 0);
+      if (!G.nwl[7]) break;
+      if (G.plastic)
+        hipLaunchKernelGGL((k_sdiv<R, 1>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[7]);
+      else
+        hipLaunchKernelGGL((k_sdiv<R, 0>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[7]);
       break;
-    case 1: if (G.nwl[1]) hipLaunchKernelGGL(k_div<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]); break;
-    case 2: hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
-    case 3: if (G.nwl[1]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]); break;
-    case 4: hipLaunchKernelGGL(k_alpha, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
+    case 1: hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
+    case 2: if (G.nwl[1]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]); break;
+    case 3: hipLaunchKernelGGL(k_alpha, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
     default: {
-      const int pk = k - 5;    // 0 x fwd, 1 y fwd, 2 z, 3 y inv, 4 x inv
+      const int pk = k - 4;    // 0 x fwd, 1 y fwd, 2 z, 3 y inv, 4 x inv
       for (int b = 0; b < NBUCKET; ++b)
         if (G.bn[pk][b]) {
           const int rc = launch_pass<R>(G, pk, b);
@@ -795,8 +816,8 @@ int launch_iterations(const Group& G, int count) {
 template <typename R>
 int launch_commit_t(fm_plan* p) {
   const Group& G = *p->self;
-  if (G.plastic) hipLaunchKernelGGL((k_stress<R, 1>), dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0], 1);
-  else hipLaunchKernelGGL((k_stress<R, 0>), dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0], 1);
+  if (G.plastic) hipLaunchKernelGGL((k_commit<R, 1>), dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0]);
+  else hipLaunchKernelGGL((k_commit<R, 0>), dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0]);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -940,7 +961,6 @@ int fm_plan_create(const fm_plan_desc* desc, void* d_workspace, size_t ws_bytes,
   s.uf = (double*)(ws + p->lay.uf);
   s.Dring = ws + p->lay.Dring;
   s.dring = ws + p->lay.dring;
-  s.sig = ws + p->lay.sig;
   s.mat = (const uint16_t*)(ws + p->lay.mat);
   s.mtab = ws + p->lay.mtab;
   s.mlaw = (const int32_t*)(ws + p->lay.mlaw);
@@ -951,6 +971,13 @@ int fm_plan_create(const fm_plan_desc* desc, void* d_workspace, size_t ws_bytes,
   s.part_d = (double*)(ws + p->lay.part_d);
   s.part_g = (double*)(ws + p->lay.part_g);
   s.ntile_s = g.ntile_s; s.ntile_d = g.ntile_d;
+  s.mixed_wrap = 0;
+  for (int i = 0; i < 3; ++i) {
+    s.sd_nt[i] = g.sd_nt[i];
+    s.wrap[i] = g.wrap[i];
+    for (int q = 0; q < 3; ++q)
+      if (g.wrap[i] && g.kinds[q][i] != K_DFT) s.mixed_wrap = 1;
+  }
   fill_pass_descs(p.get());
   rc = upload_tables(p.get());
   if (rc) return rc;
@@ -1060,7 +1087,7 @@ int fm_apply_green(fm_plan* p, const double* d_x, double* d_w) {
   }
   HIPCHK(hipMemsetAsync(p->ws + p->lay.uf, 0, 8 * n3, p->stream));
   const Group& G = *p->self;
-  for (int k = 5; k < FM_N_KERNELS; ++k) {
+  for (int k = 4; k < FM_N_KERNELS; ++k) {
     const int rc = p->d.prec == FM_FP64 ? launch_one<double>(G, k) : launch_one<float>(G, k);
     if (rc) return rc;
   }
@@ -1081,10 +1108,8 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
   HIPCHK(hipMemcpyAsync(p->ws + p->lay.uf, d_uf, 8 * n3, hipMemcpyDeviceToDevice, p->stream));
   const Group& G = *p->self;
   hipStream_t st = p->stream;
-  for (int k = 0; k < 2; ++k) {
-    rc = p->d.prec == FM_FP64 ? launch_one<double>(G, k) : launch_one<float>(G, k);
-    if (rc) return rc;
-  }
+  rc = p->d.prec == FM_FP64 ? launch_one<double>(G, 0) : launch_one<float>(G, 0);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, G.S, G.ids);
   HIPCHK(hipGetLastError());
   if (p->d.prec == FM_FP64) {

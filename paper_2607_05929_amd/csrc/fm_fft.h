@@ -28,6 +28,25 @@ template <typename R> __device__ __forceinline__ cx<R> twid(const cx<R>* W, int 
   cx<R> w = W[t];
   return inv ? conj(w) : w;   // forward uses the table value exp(-2 pi i t / L)
 }
+// Complex element idx of an interleaved global array, one 2-wide access.
+template <typename R>
+__device__ __forceinline__ cx<R> ldg(const FM_GLOBAL R* base, int64_t idx) {
+  typedef R R2 __attribute__((ext_vector_type(2)));
+  const R2 v = *(const FM_GLOBAL R2*)(base + 2 * idx);
+  return mk<R>(v.x, v.y);
+}
+template <typename R>
+__device__ __forceinline__ void stg(FM_GLOBAL R* base, int64_t idx, cx<R> c) {
+  typedef R R2 __attribute__((ext_vector_type(2)));
+  R2 v;
+  v.x = c.re; v.y = c.im;
+  *(FM_GLOBAL R2*)(base + 2 * idx) = v;
+}
+
+template <typename R> __device__ __forceinline__ cx<R> twid(const FM_GLOBAL cx<R>* W, int t, bool inv) {
+  const cx<R> w = ldg<R>((const FM_GLOBAL R*)W, t);
+  return inv ? conj(w) : w;
+}
 
 template <typename R> __device__ __forceinline__ void bfly2(cx<R>* u) {
   cx<R> a = u[0], b = u[1];

@@ -32,8 +32,8 @@ __device__ __forceinline__ void from_mandel(const R m[6], R e[6]) {
   e[0] = m[0]; e[1] = m[1]; e[2] = m[2]; e[3] = is2 * m[3]; e[4] = is2 * m[4]; e[5] = is2 * m[5];
 }
 
-template <typename R>
-__device__ __forceinline__ void mat6(const R* M, const R x[6], R y[6]) {
+template <typename R, typename PT>
+__device__ __forceinline__ void mat6(PT M, const R x[6], R y[6]) {
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     R a = 0;
@@ -52,11 +52,11 @@ __device__ __forceinline__ R powabs(R r, R n) {
 
 // Backward-Euler FCC crystal viscoplasticity (Newton on sigma_M, dGamma with
 // backtracking, started from the elastic predictor scaled to |tau|/tau_c <= 2).
-template <typename R>
-__device__ void cp_update(const R* P, const R em[6], const R epn[6], R Gn, R dt, R sm[6], R epm[6], R& Gout) {
-  const R* Cm = P;
-  const R* Sm = P + 36;
-  const R* Pm = P + 72;
+template <typename R, typename PT>
+__device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[6], R epm[6], R& Gout) {
+  const PT Cm = P;
+  const PT Sm = P + 36;
+  const PT Pm = P + 72;
   const R g0 = P[144], nx = P[145], tau0 = P[146], taus = P[147], th0 = P[148];
   R ee[6];
   R escale = (R)1e-9;
@@ -83,7 +83,7 @@ __device__ void cp_update(const R* P, const R em[6], const R epn[6], R Gn, R dt,
   auto resid = [&](const R* sg, R d, R* Rs, R& Rg, R* gd, R& tc) -> R {
     tc = tau0 + (taus - tau0) * (1 - exp(-th0 * (Gn + d) / (taus - tau0)));
     R eps_s[6];
-    mat6(Sm, sg, eps_s);
+    mat6<R>(Sm, sg, eps_s);
 #pragma unroll
     for (int i = 0; i < 6; ++i) Rs[i] = eps_s[i] - ee[i];
     R sum = 0;
@@ -183,8 +183,8 @@ __device__ void cp_update(const R* P, const R em[6], const R epn[6], R Gn, R dt,
 }
 
 // Elastic laws only (isotropic, rotated anisotropic).
-template <typename R>
-__device__ __forceinline__ void law_elastic(int law, const R* __restrict__ P, const R eps[6], R sig[6],
+template <typename R, typename PT>
+__device__ __forceinline__ void law_elastic(int law, PT P, const R eps[6], R sig[6],
                                             const R st[7], R stn[7]) {
   if (law == LAW_ISO) {
     const R lam = P[0], mu = P[1];
@@ -196,15 +196,15 @@ __device__ __forceinline__ void law_elastic(int law, const R* __restrict__ P, co
   } else {
     R em[6], sm[6];
     to_mandel(eps, em);
-    mat6(P, em, sm);
+    mat6<R>(P, em, sm);
     from_mandel(sm, sig);
   }
 #pragma unroll
   for (int i = 0; i < 7; ++i) stn[i] = st[i];
 }
 
-template <typename R>
-__device__ __forceinline__ void law_eval(int law, const R* __restrict__ P, const R eps[6], R sig[6], const R st[7],
+template <typename R, typename PT>
+__device__ __forceinline__ void law_eval(int law, PT P, const R eps[6], R sig[6], const R st[7],
                                          R stn[7], R dt) {
   if (law == LAW_ISO) {
     const R lam = P[0], mu = P[1];
@@ -218,7 +218,7 @@ __device__ __forceinline__ void law_eval(int law, const R* __restrict__ P, const
   } else if (law == LAW_ANISO) {
     R em[6], sm[6];
     to_mandel(eps, em);
-    mat6(P, em, sm);
+    mat6<R>(P, em, sm);
     from_mandel(sm, sig);
 #pragma unroll
     for (int i = 0; i < 7; ++i) stn[i] = st[i];

@@ -1,17 +1,18 @@
-// Real-space part of an iteration (Alg. 1, lines 7-10) and the per-solve
-// control logic (lines 10-18).
+// Real-space part of an iteration of Algorithm 1 (strain, behaviour law,
+// discrete divergence, equilibrium error) and the per-solve control logic
+// (convergence test, mixed loading, Anderson acceleration).
 //
-//  k_stress  voxel kernel: strain at the integration points from the node
-//            displacements (HEX1 Eqs. D1HG-D3HG; TETRA2 Eqs. D1T1T2G-D3T1T2G),
-//            plus the discrete gradient of the prescribed field, behaviour
-//            law, stress written for the divergence, FP64 block partials of
-//            sum_ip w |sigma|^2 and sum sigma (macroscopic stress).
-//  k_div     node kernel: D_q = sum_l D_l sigma_lq at the kept nodes, with
-//            the stress of the mirror voxels obtained from the symmetry /
-//            periodicity of the equation's component (Eq.
+//  k_sdiv    fused tile kernel: strain at the integration points from the
+//            node displacements (HEX1 Eqs. D1HG-D3HG; TETRA2 Eqs.
+//            D1T1T2G-D3T1T2G) plus the discrete gradient of the prescribed
+//            field, behaviour law, and D_q = sum_l D_l sigma_lq at the kept
+//            nodes, with the stress of the mirror voxels obtained from the
+//            symmetry / periodicity of the equation's component (Eq.
 //            Continuous_der_symmetry_per on the stress columns; for TETRA2
-//            the reflection exchanges the two tetrahedra), FP64 partial of
-//            sum |D|^2.
+//            the reflection exchanges the two tetrahedra); FP64 block
+//            partials of sum_ip w |sigma|^2, sum sigma and sum |D|^2.
+//  k_commit  voxel kernel of the end of an increment: internal variables,
+//            FP64 strain / stress outputs.
 //  k_gram    Gram matrix of the residual history (Anderson, FP64 partials).
 //  k_control convergence test (Eq. equilibrium_condition), macroscopic
 //            stress, mixed loading update, Anderson schedule.
@@ -73,83 +74,134 @@ __device__ __forceinline__ bool node_kept(int kind, int n, int j) {
   }
 }
 
-// mode 0: iteration; mode 1: commit (state update + FP64 outputs).
-// PL = 0 compiles the elastic laws only (no internal variables), PL = 1 all laws.
-template <typename R, int PL>
-__global__ void __launch_bounds__(256) k_stress(const SolveDev* __restrict__ S, const int2* __restrict__ work, int mode) {
-  const int2 w = work[blockIdx.x];
-  const SolveDev& s = S[w.x];
-  const Ctrl* C = s.ctrl;
-  if (mode == 0 && C->status != ST_RUNNING) return;
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int sub = 0; sub < SPACE_TILE / 256; ++sub) {
-  const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
-  if (v < s.Nv) {
-    const int n0 = s.n[0], n1 = s.n[1];
-    const int x = (int)(v % n0);
-    const int64_t t = v / n0;
-    const int y = (int)(t % n1), z = (int)(t / n1);
-    const int64_t N0 = s.N[0], N01 = (int64_t)s.N[0] * s.N[1];
-    const int64_t base = z * N01 + (int64_t)y * N0 + x;
-    double u[3][8];
+// Strain at the integration points of voxel (x, y, z) from the node
+// displacements u^f plus the discrete gradient of the prescribed field u*
+// (HEX1: one point, all corners, weight (2a_l - 1)/(4h); TETRA2: T1 on the
+// even corners and T2 on the odd corners, weight (2a_l - 1)/(2h)).
+// FP64: the corner sums are taken in FP64.  FP32: each corner value enters
+// as its FP64 difference to corner (0,0,0), rounded once (the stencil
+// weights of one point sum to zero, so only differences matter), and the
+// rest is FP32.
+// Discrete gradient, on one tetrahedron of TETRA2, of the cross terms
+// x_a x_b of u*: hc[l][q] enters with - on T1 and + on T2 (0 for HEX1).
+template <typename R>
+__device__ __forceinline__ void tet_cross_terms(const SolveDev& s, const FM_GLOBAL Ctrl* C, R (&hc)[3][3]) {
+  const double c = s.scheme == 1 ? 0.5 * s.h : 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    hc[0][q] = (R)(c * C->H[(q * 3 + 1) * 3 + 2]);
+    hc[1][q] = (R)(c * C->H[(q * 3 + 0) * 3 + 2]);
+    hc[2][q] = (R)(c * C->H[(q * 3 + 0) * 3 + 1]);
+  }
+}
+
+// u* gradient at voxel centres of one column (x, y): gs = gA + gB z_c.
+template <typename R>
+__device__ __forceinline__ void ustar_grad_column(const SolveDev& s, const FM_GLOBAL Ctrl* C, int x, int y,
+                                                  R (&gA)[3][3], R (&gB)[3][3]) {
+  const double xc = (x + 0.5) * s.h, yc = (y + 0.5) * s.h;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      const double* uq = s.uf + q * s.Nn;
-#pragma unroll
-      for (int cidx = 0; cidx < 8; ++cidx) {
-        const int a = cidx & 1, b = (cidx >> 1) & 1, c = cidx >> 2;
-        u[q][cidx] = uq[base + a + b * N0 + c * N01];
-      }
+      const FM_GLOBAL double* H = C->H + (q * 3 + l) * 3;
+      gA[l][q] = (R)(C->G[q * 3 + l] + H[0] * xc + H[1] * yc);
+      gB[l][q] = (R)H[2];
     }
-    const double h = s.h;
-    const double xc[3] = {(x + 0.5) * h, (y + 0.5) * h, (z + 0.5) * h};
-    // gradient of u* at the voxel centre
-    double gs[3][3];
+}
+
+// Corner values of voxel (x, y, z): u[q][c] for FP64; for FP32 the FP64
+// difference to corner 0, rounded once (the stencil weights of one point sum
+// to zero, so only differences matter).
+template <typename R>
+__device__ __forceinline__ void voxel_corners(const SolveDev& s, int x, int y, int z, R (&u)[3][8]) {
+  const int64_t N0 = s.N[0], N01 = (int64_t)s.N[0] * s.N[1];
+  const int64_t base = z * N01 + (int64_t)y * N0 + x;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const FM_GLOBAL double* uq = gconst(s.uf) + q * s.Nn + base;
+    const double u0 = uq[0];
+    u[q][0] = sizeof(R) == 8 ? (R)u0 : (R)0;
+#pragma unroll
+    for (int cidx = 1; cidx < 8; ++cidx) {
+      const int a = cidx & 1, b = (cidx >> 1) & 1, c = cidx >> 2;
+      const double uc = uq[a + b * N0 + c * N01];
+      u[q][cidx] = sizeof(R) == 8 ? (R)uc : (R)(uc - u0);
+    }
+  }
+}
+
+// Strain at the integration points (HEX1: one point, all corners, weight
+// (2a_l - 1)/(4h); TETRA2: T1 on the even corners and T2 on the odd corners,
+// weight (2a_l - 1)/(2h)) from the corner values, the u* gradient at the
+// voxel centre and the tetrahedron cross-term correction.
+template <typename R>
+__device__ __forceinline__ void strain_from_corners(const SolveDev& s, const R (&u)[3][8], const R (&gs)[3][3],
+                                                    const R (&hc)[3][3], R eps[2][6]) {
+  const R f = (R)((s.scheme == 0) ? 0.25 / s.h : 0.5 / s.h);
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    if (r >= s.nppv) break;
+    R g[3][3];
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        double g = C->G[q * 3 + l];
+        R a = 0;
 #pragma unroll
-        for (int m = 0; m < 3; ++m) g += C->H[(q * 3 + l) * 3 + m] * xc[m];
-        gs[l][q] = g;
+        for (int cidx = 0; cidx < 8; ++cidx) {
+          const int bit[3] = {cidx & 1, (cidx >> 1) & 1, cidx >> 2};
+          const int par = (bit[0] + bit[1] + bit[2]) & 1;
+          if (s.scheme == 1 && par != r) continue;
+          a += bit[l] ? u[q][cidx] : -u[q][cidx];
+        }
+        g[l][q] = a * f + gs[l][q] + (r == 0 ? -hc[l][q] : hc[l][q]);
       }
-    const int mt = s.mat[v];
-    const int law = s.mlaw[mt];
-    const R* P = (const R*)s.mtab + (int64_t)mt * MT_STRIDE;
-    const double wip = 1.0 / s.nppv;
+    eps[r][0] = g[0][0]; eps[r][1] = g[1][1]; eps[r][2] = g[2][2];
+    eps[r][3] = (R)0.5 * (g[1][2] + g[2][1]);
+    eps[r][4] = (R)0.5 * (g[0][2] + g[2][0]);
+    eps[r][5] = (R)0.5 * (g[0][1] + g[1][0]);
+  }
+}
+
+// Strain at the integration points of voxel (x, y, z).
+template <typename R>
+__device__ __forceinline__ void voxel_strain(const SolveDev& s, const FM_GLOBAL Ctrl* C, int x, int y, int z, R eps[2][6]) {
+  R u[3][8], gA[3][3], gB[3][3], hc[3][3];
+  voxel_corners<R>(s, x, y, z, u);
+  ustar_grad_column<R>(s, C, x, y, gA, gB);
+  tet_cross_terms<R>(s, C, hc);
+  const R zc = (R)((z + 0.5) * s.h);
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) gA[l][q] += gB[l][q] * zc;
+  strain_from_corners<R>(s, u, gA, hc, eps);
+}
+
+// Commit of an increment: behaviour law with the converged strain, internal
+// variables stored, FP64 strain / stress outputs.  PL = 0 compiles the
+// elastic laws only, PL = 1 all laws.
+template <typename R, int PL>
+__global__ void __launch_bounds__(256) k_commit(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const SolveDev& s = S[w.x];
+  const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
+  for (int sub = 0; sub < SPACE_TILE / 256; ++sub) {
+    const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
+    if (v >= s.Nv) continue;
+    const int n0 = s.n[0], n1 = s.n[1];
+    const int x = (int)(v % n0);
+    const int64_t t = v / n0;
+    const int y = (int)(t % n1), z = (int)(t / n1);
+    R eps[2][6];
+    voxel_strain<R>(s, C, x, y, z, eps);
+    const int mt = gconst(s.mat)[v];
+    const int law = gconst(s.mlaw)[mt];
+    const FM_GLOBAL R* P = gconst((const R*)s.mtab) + (int64_t)mt * MT_STRIDE;
     for (int r = 0; r < s.nppv; ++r) {
-      double g[3][3];
-      const double f = (s.scheme == 0) ? 0.25 / h : 0.5 / h;
-#pragma unroll
-      for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          double a = 0;
-#pragma unroll
-          for (int cidx = 0; cidx < 8; ++cidx) {
-            const int bit[3] = {cidx & 1, (cidx >> 1) & 1, cidx >> 2};
-            const int par = (bit[0] + bit[1] + bit[2]) & 1;
-            // HEX1: all corners; TETRA2: T1 = even corners, T2 = odd corners
-            if (s.scheme == 1 && par != r) continue;
-            a += bit[l] ? u[q][cidx] : -u[q][cidx];
-          }
-          g[l][q] = a * f + gs[l][q];
-        }
-      if (s.scheme == 1) {
-        // discrete gradient of the cross terms x_a x_b of u* on one tetrahedron
-        const double corr = (r == 0 ? -0.5 : 0.5) * h;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          g[0][q] += corr * C->H[(q * 3 + 1) * 3 + 2];
-          g[1][q] += corr * C->H[(q * 3 + 0) * 3 + 2];
-          g[2][q] += corr * C->H[(q * 3 + 0) * 3 + 1];
-        }
-      }
-      R eps[6] = {(R)g[0][0], (R)g[1][1], (R)g[2][2], (R)(0.5 * (g[1][2] + g[2][1])),
-                  (R)(0.5 * (g[0][2] + g[2][0])), (R)(0.5 * (g[0][1] + g[1][0]))};
       R st[7], stn[7];
-      R* state = (R*)s.state;
+      FM_GLOBAL R* state = gmut((R*)s.state);
       if (PL && s.has_state) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) st[k] = state[((int64_t)k * s.nppv + r) * s.Nv + v];
@@ -158,116 +210,212 @@ __global__ void __launch_bounds__(256) k_stress(const SolveDev* __restrict__ S, 
         for (int k = 0; k < 7; ++k) st[k] = 0;
       }
       R sig[6];
-      if (PL) law_eval<R>(law, P, eps, sig, st, stn, (R)C->dt);
-      else law_elastic<R>(law, P, eps, sig, st, stn);
-      if (mode == 0) {
-        R* so = (R*)s.sig;
+      if (PL) law_eval<R>(law, P, eps[r], sig, st, stn, (R)C->dt);
+      else law_elastic<R>(law, P, eps[r], sig, st, stn);
+      if (PL && s.has_state && (law == LAW_J2 || law == LAW_CP)) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) so[((int64_t)k * s.nppv + r) * s.Nv + v] = sig[k];
-        double n2 = 0;
+        for (int k = 0; k < 7; ++k) state[((int64_t)k * s.nppv + r) * s.Nv + v] = stn[k];
+      }
+      if (s.out_eps) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const double sk = sig[k];
-          n2 += (k < 3 ? 1.0 : 2.0) * sk * sk;
-          acc[1 + k] += wip * sk;
-        }
-        acc[0] += wip * n2;
-      } else {
-        if (PL && s.has_state && (law == LAW_J2 || law == LAW_CP)) {
+        for (int k = 0; k < 6; ++k) gmut(s.out_eps)[((int64_t)k * s.nppv + r) * s.Nv + v] = (double)eps[r][k];
+      }
+      if (s.out_sig) {
 #pragma unroll
-          for (int k = 0; k < 7; ++k) state[((int64_t)k * s.nppv + r) * s.Nv + v] = stn[k];
-        }
-        if (s.out_eps) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) s.out_eps[((int64_t)k * s.nppv + r) * s.Nv + v] = (double)eps[k];
-        }
-        if (s.out_sig) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) s.out_sig[((int64_t)k * s.nppv + r) * s.Nv + v] = (double)sig[k];
-        }
+        for (int k = 0; k < 6; ++k) gmut(s.out_sig)[((int64_t)k * s.nppv + r) * s.Nv + v] = (double)sig[k];
       }
     }
-  }
-  }
-  if (mode == 0) {
-    __shared__ double outp[7];
-    block_sum<7>(acc, outp);
-    __syncthreads();
-    if (threadIdx.x < 7) s.part_s[(int64_t)w.y * NPART_S + threadIdx.x] = outp[threadIdx.x];
   }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_div(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
-  const int2 w = work[blockIdx.x];
-  const SolveDev& s = S[w.x];
-  const Ctrl* C = s.ctrl;
-  if (C->status != ST_RUNNING) return;
-  double acc[1] = {0};
-  for (int sub = 0; sub < SPACE_TILE / 256; ++sub) {
-  const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
-  if (v < s.Nn) {
-    const int N0 = s.N[0], N1 = s.N[1];
-    const int J[3] = {(int)(v % N0), (int)((v / N0) % N1), (int)(v / ((int64_t)N0 * N1))};
-    const R* sg = (const R*)s.sig;
-    R* Dout = (R*)s.Dring + (int64_t)(C->m % s.depth) * 3 * s.Nn;
-    const R f = (R)(0.25 / s.h);
-    for (int q = 0; q < 3; ++q) {
-      bool kept = true;
+// ---------------------------------------------------------------------------
+// Fused stress + divergence of one iteration.
+//
+// A block owns a tile of SD_TX x SD_TY node columns and SD_ZC node layers.
+// It marches up the layers: for voxel layer z it evaluates the behaviour law
+// on the 32 x 8 voxels that touch the tile (one per thread, the tile plus a
+// one-voxel halo) into an LDS ring of two voxel layers, then forms the
+// divergence at node layer z from voxel layers z-1 and z.  The stress never
+// goes to memory.  Outside the grid a halo voxel holds the periodic image
+// along axes periodic for some component, and zero otherwise (see
+// node_div for the reflecting faces).  Every voxel's stress enters the
+// block partials (sum w |sigma|^2, sum sigma) exactly once, in the tile that
+// owns node (x, y, z) of its lower corner; the partials also carry
+// sum |D|^2.
+// ---------------------------------------------------------------------------
+constexpr int SD_TX = 31, SD_TY = 7, SD_ZC = 16;   // node tile; voxel tile 32 x 8
+constexpr int SD_VT = 256;                          // voxels per layer tile
+
+__device__ __forceinline__ int map_vox(int g, int n, int wrap) {
+  if (g < 0) return wrap ? n - 1 : 0;
+  if (g >= n) return wrap ? min(g - n, n - 1) : n - 1;
+  return g;
+}
+
+// Divergence at node J from the two voxel layers of the ring.  Faces: a
+// node kept for component q sits on a reflecting face of q only where u_q is
+// symmetric (an anti-symmetric face dismisses the node), and there each
+// mirror corner contributes exactly what its in-grid image contributes (the
+// T1/T2 exchange and the signs of Eq. Continuous_der_symmetry_per cancel the
+// flipped stencil sign).  So the mirror corners are dropped and the sum is
+// doubled per reflecting face.  Mirror corners are dropped through halo
+// slots holding zero (axes periodic for no component) or, on axes periodic
+// for another component, through a per-corner mask; periodic components
+// read their halo slot (the periodic image voxel) as in the interior.
+// Mask bits of mirror corners to drop on axes periodic for another
+// component: bit (q * 6 + 2 * i + b) set when corner side b of axis i is
+// outside the grid at this node and u_q is not periodic along i.
+__device__ __forceinline__ int drop_bits(const SolveDev& s, const int J[3]) {
+  int m = 0;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) kept = kept && node_kept(s.kinds[q][i], s.n[i], J[i]);
-      R D = 0;
-      if (kept) {
-        for (int cidx = 0; cidx < 8; ++cidx) {
-          const int bit[3] = {cidx & 1, (cidx >> 1) & 1, cidx >> 2};
-          int vi[3];
-          int nref = 0;
-          R sgn[3] = {1, 1, 1};
+  for (int q = 0; q < 3; ++q)
 #pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            int idx = J[i] - 1 + bit[i];
-            if (idx < 0 || idx >= s.n[i]) {
-              const int side = idx < 0 ? 0 : 1;
-              const int e = face_ext(s.kinds[q][i], side);
-              if (e == 0) {
-                idx = idx < 0 ? s.n[i] - 1 : 0;
-              } else {
-                idx = idx < 0 ? 0 : s.n[i] - 1;
-                ++nref;
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                  // symmetric u_q: + for l != i; anti-symmetric: + for l == i
-                  const bool plus = (e == 1) ? (l != i) : (l == i);
-                  if (!plus) sgn[l] = -sgn[l];
-                }
-              }
-            }
-            vi[i] = idx;
-          }
-          int r = 0;
-          if (s.scheme == 1) {
-            const int par = (bit[0] + bit[1] + bit[2]) & 1;
-            r = par ? 0 : 1;            // odd corners take T1 values, even corners T2
-            if (nref & 1) r ^= 1;       // a reflection exchanges T1 and T2
-          }
-          const int64_t vox = ((int64_t)vi[2] * s.n[1] + vi[1]) * s.n[0] + vi[0];
-#pragma unroll
-          for (int l = 0; l < 3; ++l) {
-            const R val = sg[((int64_t)vidx(l, q) * s.nppv + r) * s.Nv + vox] * sgn[l];
-            D += bit[l] ? val : -val;
-          }
-        }
-        D *= f;
-        acc[0] += (double)D * (double)D;
+    for (int i = 0; i < 3; ++i)
+      if (s.wrap[i] && s.kinds[q][i] != K_DFT) {
+        if (J[i] == 0) m |= 1 << (q * 6 + 2 * i);
+        if (J[i] == s.n[i]) m |= 1 << (q * 6 + 2 * i + 1);
       }
-      Dout[q * s.Nn + v] = D;
+  return m;
+}
+
+template <typename R>
+__device__ __forceinline__ void node_div(const SolveDev& s, const FM_GLOBAL Ctrl* C, const R* __restrict__ sl, int cur,
+                                         int lx, int ly, const int J[3], R& accD) {
+  constexpr int PL_ = 12 * SD_VT;            // reals per voxel layer in the ring
+  const R* lay[2] = {sl + (cur ^ 1) * PL_, sl + cur * PL_};   // voxel layer J2 - 1, J2
+  const int64_t node = ((int64_t)J[2] * s.N[1] + J[1]) * s.N[0] + J[0];
+  FM_GLOBAL R* Dout = gmut((R*)s.Dring) + (int64_t)(C->m % s.depth) * 3 * s.Nn;
+  R D[3] = {0, 0, 0};
+  const int dm = s.mixed_wrap ? drop_bits(s, J) : 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
+    const int r = (s.scheme == 1) ? (((b0 + b1 + b2) & 1) ? 0 : 1) : 0;   // odd corners T1, even T2
+    const R* p = lay[b2] + 6 * r * SD_VT + (ly + b1) * 32 + (lx + b0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      R t = 0;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const R val = p[vidx(l, q) * SD_VT];
+        const int bl = l == 0 ? b0 : (l == 1 ? b1 : b2);
+        t += bl ? val : -val;
+      }
+      const int cm = (1 << (q * 6 + b0)) | (1 << (q * 6 + 2 + b1)) | (1 << (q * 6 + 4 + b2));
+      D[q] += (dm & cm) ? (R)0 : t;
     }
   }
+  const R f = (R)(0.25 / s.h);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    bool kept = true;
+    R fq = f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      kept = kept && node_kept(s.kinds[q][i], s.n[i], J[i]);
+      if (s.kinds[q][i] != K_DFT && (J[i] == 0 || J[i] == s.n[i])) fq *= (R)2;
+    }
+    const R Dq = kept ? D[q] * fq : (R)0;
+    accD += Dq * Dq;
+    Dout[q * s.Nn + node] = Dq;
   }
-  __shared__ double outp[1];
-  block_sum<1>(acc, outp);
+}
+
+// Bytes of dynamic LDS of k_sdiv.
+__host__ __device__ inline size_t sdiv_lds_bytes(int rbytes) { return (size_t)2 * 12 * SD_VT * rbytes; }
+
+template <typename R, int PL>
+__global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const SolveDev& s = S[w.x];
+  const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
+  if (C->status != ST_RUNNING) return;
+  extern __shared__ __align__(16) char smem[];
+  R* sl = (R*)smem;                                    // [2 layers][12][SD_VT]
+  const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
+  const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * SD_ZC;
+  const int Z1 = min(Z0 + SD_ZC, s.N[2]);
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  const int n0 = s.n[0], n1 = s.n[1], n2 = s.n[2];
+  const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
+  const int vx = map_vox(gx, n0, s.wrap[0]), vy = map_vox(gy, n1, s.wrap[1]);
+  const bool own_xy = lx >= 1 && ly >= 1 && gx < n0 && gy < n1;
+  const bool zero_xy = (!s.wrap[0] && (gx < 0 || gx >= n0)) || (!s.wrap[1] && (gy < 0 || gy >= n1));
+  const int J0 = X0 + lx, J1 = Y0 + ly;
+  const bool has_node = lx < SD_TX && ly < SD_TY && J0 < s.N[0] && J1 < s.N[1];
+  const FM_GLOBAL uint16_t* mat = gconst(s.mat);
+  const R wip = (R)1 / (R)s.nppv;
+  // per-thread partials in R (each thread sums at most 2 (SD_ZC + 1) points),
+  // FP64 across the block
+  R acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  R gA[3][3], gB[3][3], hc[3][3];
+  ustar_grad_column<R>(s, C, vx, vy, gA, gB);
+  tet_cross_terms<R>(s, C, hc);
+  int mt_cur = mat[((int64_t)map_vox(Z0 - 1, n2, s.wrap[2]) * n1 + vy) * n0 + vx];
+  for (int zl = Z0 - 1; zl < Z1; ++zl) {
+    const int slot = (zl + 2) & 1;
+    // material of the next voxel layer, fetched one layer ahead
+    const int mt_next = (zl + 1 < Z1) ? (int)mat[((int64_t)map_vox(zl + 1, n2, s.wrap[2]) * n1 + vy) * n0 + vx] : 0;
+    {
+      const int vz = map_vox(zl, n2, s.wrap[2]);
+      const int law = gconst(s.mlaw)[mt_cur];
+      const FM_GLOBAL R* P = gconst((const R*)s.mtab) + (int64_t)mt_cur * MT_STRIDE;
+      R eps[2][6];
+      {
+        R u[3][8], gs[3][3];
+        voxel_corners<R>(s, vx, vy, vz, u);
+        const R zc = (R)((vz + 0.5) * s.h);
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) gs[l][q] = gA[l][q] + gB[l][q] * zc;
+        strain_from_corners<R>(s, u, gs, hc, eps);
+      }
+      const int64_t v = ((int64_t)vz * n1 + vy) * n0 + vx;
+      const bool own = own_xy && zl >= Z0 && zl < n2;
+      const bool zero_halo = zero_xy || (!s.wrap[2] && (zl < 0 || zl >= n2));
+      R* out = sl + slot * 12 * SD_VT + threadIdx.x;
+      for (int r = 0; r < s.nppv; ++r) {
+        R st[7], stn[7], sig[6];
+        if (PL && s.has_state) {
+          const FM_GLOBAL R* state = gconst((const R*)s.state);
+#pragma unroll
+          for (int k = 0; k < 7; ++k) st[k] = state[((int64_t)k * s.nppv + r) * s.Nv + v];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 7; ++k) st[k] = 0;
+        }
+        if (PL) law_eval<R>(law, P, eps[r], sig, st, stn, (R)C->dt);
+        else law_elastic<R>(law, P, eps[r], sig, st, stn);
+        // halo voxels across faces of axes periodic for no component hold zero
+#pragma unroll
+        for (int k = 0; k < 6; ++k) out[(6 * r + k) * SD_VT] = zero_halo ? (R)0 : sig[k];
+        if (own) {
+          R n2s = 0;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            n2s += (k < 3 ? (R)1 : (R)2) * sig[k] * sig[k];
+            acc[1 + k] += wip * sig[k];
+          }
+          acc[0] += wip * n2s;
+        }
+      }
+    }
+    __syncthreads();
+    if (zl >= Z0 && has_node) {
+      const int J[3] = {J0, J1, zl};
+      node_div<R>(s, C, sl, slot, lx, ly, J, acc[7]);
+    }
+    mt_cur = mt_next;
+    __syncthreads();
+  }
+  __shared__ double outp[8];
+  double accd[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) accd[i] = (double)acc[i];
+  block_sum<8>(accd, outp);
   __syncthreads();
-  if (threadIdx.x == 0) s.part_d[w.y] = outp[0];
+  if (threadIdx.x < 8) gmut(s.part_s)[(int64_t)w.y * NPART_S + threadIdx.x] = outp[threadIdx.x];
 }
 
 template <typename R>
@@ -317,8 +465,7 @@ __global__ void __launch_bounds__(256) k_control(const SolveDev* __restrict__ S,
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int t = threadIdx.x; t < s.ntile_s; t += blockDim.x)
 #pragma unroll
-    for (int i = 0; i < 7; ++i) a[i] += s.part_s[(int64_t)t * NPART_S + i];
-  for (int t = threadIdx.x; t < s.ntile_d; t += blockDim.x) a[7] += s.part_d[t];
+    for (int i = 0; i < 8; ++i) a[i] += s.part_s[(int64_t)t * NPART_S + i];
   __shared__ double tot[8];
   block_sum<8>(a, tot);
   __syncthreads();

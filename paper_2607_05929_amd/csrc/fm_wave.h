@@ -1,23 +1,27 @@
 // Wavefront-per-pencil axis passes for pencil lengths L = 64 E (E in
 // {1, 2, 3, 4, 5, 6, 8, 12, 16}), the common case of the solver's grids.
 //
-// A block of 16 wavefronts owns a tile of 16 pencils (32 real columns packed
-// two per pencil, or 16 complex columns).  The tile is loaded with
-// coalesced 128-byte rows into an LDS staging array; each wavefront then
-// gathers its pencil's virtual extension (Table 1) straight into registers,
-// lane t holding positions t + 64 j (j < E), and transforms it with
+// A block of 8 wavefronts owns a tile of 8 pencils (16 real columns packed
+// two per pencil, or 8 complex columns): small blocks so that several fit a
+// compute unit and one block's loads overlap another's arithmetic.  The tile
+// is loaded with coalesced 64-byte row segments (whole rows along x) into an
+// LDS staging array; each wavefront then gathers its pencil's virtual
+// extension (Table 1) straight into registers, lane t holding positions
+// t + 64 j (j < E), and transforms it with
 //   X[k1 + E k2] = sum_t W_L^{t k1} W_64^{t k2} sum_j x[t + 64 j] W_E^{j k1}:
 // an E-point DFT in registers, a twiddle, and a 64-point DFT across the
-// lanes (radix-2 butterflies through lane shuffles, then a bit-reversal
-// shuffle).  The Green operator of the fused z pass scales the spectrum in
-// registers.  Results go back through the staging array to coalesced stores.
-// No block barrier separates FFT stages; the staging array is the only LDS.
+// lanes (radix-2 butterflies through lane exchanges, decimation in frequency
+// forward and in time inverse, so the spectrum stays in bit-reversed lane
+// order and needs no reordering).  The Green operator of the fused z pass
+// scales the spectrum in registers.  Results go back through the staging
+// array to coalesced stores.  No block barrier separates FFT stages; the
+// staging array is the only LDS.
 #pragma once
 #include "fm_pass.h"
 
 namespace fm {
 
-constexpr int WAVE_PENCILS = 16;        // wavefronts (pencils) per block
+constexpr int WAVE_PENCILS = 8;         // wavefronts (pencils) per block
 constexpr int WAVE_THREADS = 64 * WAVE_PENCILS;
 
 __host__ __device__ inline bool wave_E_ok(int E) {
@@ -47,14 +51,14 @@ struct LaneTw {
 };
 
 template <typename R>
-__device__ __forceinline__ LaneTw<R> lane_twiddles(const cx<R>* W, int L) {
+__device__ __forceinline__ LaneTw<R> lane_twiddles(const FM_GLOBAL cx<R>* W, int L) {
   const int lane = threadIdx.x & 63;
   LaneTw<R> tw;
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     const int h = 32 >> i;
     tw.sg[i] = (lane & h) ? (R)-1 : (R)1;
-    if (i < 5) tw.s[i] = (lane & h) ? W[(lane & (h - 1)) * (L / (2 * h))] : mk<R>(1, 0);
+    if (i < 5) tw.s[i] = (lane & h) ? twid<R>(W, (lane & (h - 1)) * (L / (2 * h)), false) : mk<R>(1, 0);
   }
   return tw;
 }
@@ -102,7 +106,7 @@ __device__ __forceinline__ void lane_dit64(cx<R> (&v)[E], const LaneTw<R>& tw) {
 
 // In-register E-point DFT (natural order in and out).
 template <typename R, int E>
-__device__ __forceinline__ void dft_reg(cx<R> (&v)[E], const cx<R>* W, int L, bool inv) {
+__device__ __forceinline__ void dft_reg(cx<R> (&v)[E], const FM_GLOBAL cx<R>* W, int L, bool inv) {
   const R sgn = inv ? (R)1 : (R)-1;
   if constexpr (E == 1) {
     return;
@@ -148,18 +152,18 @@ __device__ __forceinline__ void dft_reg(cx<R> (&v)[E], const cx<R>* W, int L, bo
 // X[k1 + E brev6(t)] in v[k1].  Inverse: the exact mirror image (input in
 // that bit-reversed layout, output x[t + 64 j] in v[j], unnormalised).
 template <typename R, int E>
-__device__ __forceinline__ void wave_fft(cx<R> (&v)[E], const cx<R>* W, const LaneTw<R>& tw, bool inv) {
+__device__ __forceinline__ void wave_fft(cx<R> (&v)[E], const FM_GLOBAL cx<R>* W, const LaneTw<R>& tw, bool inv) {
   constexpr int L = 64 * E;
   const int t = threadIdx.x & 63;
   if (!inv) {
     dft_reg<R, E>(v, W, L, false);
 #pragma unroll
-    for (int k1 = 1; k1 < E; ++k1) v[k1] = mul(v[k1], W[t * k1]);
+    for (int k1 = 1; k1 < E; ++k1) v[k1] = mul(v[k1], twid<R>(W, t * k1, false));
     lane_dif64<R, E>(v, tw);
   } else {
     lane_dit64<R, E>(v, tw);
 #pragma unroll
-    for (int k1 = 1; k1 < E; ++k1) v[k1] = mul(v[k1], conj(W[t * k1]));
+    for (int k1 = 1; k1 < E; ++k1) v[k1] = mul(v[k1], twid<R>(W, t * k1, true));
     dft_reg<R, E>(v, W, L, true);
   }
 }
@@ -195,7 +199,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   __shared__ GreenCol<R> gcol[32];
   const int2 wk = work[blockIdx.x];
   const PassDesc& d = descs[wk.x];
-  const Ctrl* C = S[d.solve].ctrl;
+  const FM_GLOBAL Ctrl* C = gconst(S[d.solve].ctrl);
   if (C->status != ST_RUNNING) return;
   constexpr int L = 64 * E;
   const int n = d.n, kind = d.kind;
@@ -209,7 +213,9 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   if (XP) { tl.p0b = wk.y * cols; tl.p1 = 0; }
   else { tl.p0b = (wk.y % d.tiles_p0) * cols; tl.p1 = wk.y / d.tiles_p0; }
   tl.ncol = min(cols, d.n_p0 - tl.p0b);
-  const cx<R>* W = (const cx<R>*)d.tw;
+  const FM_GLOBAL cx<R>* W = gconst((const cx<R>*)d.tw);
+  const FM_GLOBAL R* gin = gconst((const R*)d.in);
+  FM_GLOBAL R* gout = gmut((R*)d.out);
   const LaneTw<R> ltw = lane_twiddles<R>(W, L);
   R* sr = (R*)smem;            // staging, real elements (packed)
   cx<R>* sc = (cx<R>*)smem;    // staging, complex elements
@@ -226,12 +232,12 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   {
     const int nd = (XP && MODE == 0) ? C->n_d : 0;
     R al[MAX_DEPTH];
-    const R* src[MAX_DEPTH];
+    const FM_GLOBAL R* src[MAX_DEPTH];
     if (XP && MODE == 0) {
 #pragma unroll
       for (int q = 0; q < MAX_DEPTH; ++q) {
         al[q] = q < nd ? (R)C->alpha[q] : (R)0;
-        src[q] = (const R*)d.ring + (int64_t)(q < nd ? C->slot_d[q] : 0) * d.ring_stride;
+        src[q] = gconst((const R*)d.ring) + (int64_t)(q < nd ? C->slot_d[q] : 0) * d.ring_stride;
       }
     }
     // Loads are issued in batches of U per thread before any is written to
@@ -265,7 +271,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
             for (int u = 0; u < U; ++u) {
               const int e = eb + 64 * u;
               tv[u] = mk<R>(0, 0);
-              if (okc && e < cnt) tv[u] = ldc<R>(d.in, addr<1>(tl, c, j0 + e, 0, d.in_s1));
+              if (okc && e < cnt) tv[u] = ldg<R>(gin, addr<1>(tl, c, j0 + e, 0, d.in_s1));
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -276,7 +282,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
             for (int u = 0; u < U; ++u) {
               const int e = eb + 64 * u;
               tv[u] = 0;
-              if (okc && e < cnt) tv[u] = ((const R*)d.in)[addr<1>(tl, c, j0 + e, 0, d.in_s1)];
+              if (okc && e < cnt) tv[u] = gin[addr<1>(tl, c, j0 + e, 0, d.in_s1)];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -296,7 +302,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
           for (int u = 0; u < U; ++u) {
             const int e = eb + u * step;
             tv[u] = mk<R>(0, 0);
-            if (okc && e < cnt) tv[u] = ldc<R>(d.in, addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1));
+            if (okc && e < cnt) tv[u] = ldg<R>(gin, addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1));
           }
 #pragma unroll
           for (int u = 0; u < U; ++u)
@@ -307,7 +313,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
           for (int u = 0; u < U; ++u) {
             const int e = eb + u * step;
             tv[u] = 0;
-            if (okc && e < cnt) tv[u] = ((const R*)d.in)[addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1)];
+            if (okc && e < cnt) tv[u] = gin[addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1)];
           }
 #pragma unroll
           for (int u = 0; u < U; ++u)
@@ -366,9 +372,9 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
     // Green operator on the spectrum held in registers (lane t, register k1:
     // position m = k1 + E brev6(t)); same structure-preserving scaling as the
     // generic pass.
-    const double* zs2 = d.gs2[2];
-    const double* zc2 = d.gc2[2];
-    const uint8_t* zfl = d.gfl[2];
+    const FM_GLOBAL double* zs2 = gconst(d.gs2[2]);
+    const FM_GLOBAL double* zc2 = gconst(d.gc2[2]);
+    const FM_GLOBAL uint8_t* zfl = gconst(d.gfl[2]);
     const bool okA = ca < tl.ncol, okB = packed ? cb < tl.ncol : false;
     if (half) {
       cx<R> nv[E];
@@ -480,7 +486,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
               if (eb + 64 * u < outcnt) tv[u] = sc[sidx<1>(c, eb + 64 * u, opitch)];
 #pragma unroll
             for (int u = 0; u < UD; ++u)
-              if (eb + 64 * u < outcnt) stc<R>(d.out, addr<1>(tl, c, eb + 64 * u, d.out_sa, d.out_s1), tv[u]);
+              if (eb + 64 * u < outcnt) stg<R>(gout, addr<1>(tl, c, eb + 64 * u, d.out_sa, d.out_s1), tv[u]);
           } else {
             R tv[UD];
 #pragma unroll
@@ -488,20 +494,21 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
               if (eb + 64 * u < outcnt) tv[u] = sr[sidx<1>(c, eb + 64 * u, opitch)];
 #pragma unroll
             for (int u = 0; u < UD; ++u)
-              if (eb + 64 * u < outcnt) ((R*)d.out)[addr<1>(tl, c, eb + 64 * u, d.out_sa, d.out_s1)] = tv[u];
+              if (eb + 64 * u < outcnt) gout[addr<1>(tl, c, eb + 64 * u, d.out_sa, d.out_s1)] = tv[u];
           }
         }
     } else {
       // x inverse: u^f += w - sum_k beta_k delta_k, new increment into the ring
       const int nb = C->n_b;
       R be[MAX_DEPTH];
-      const R* dsrc[MAX_DEPTH];
+      const FM_GLOBAL R* dsrc[MAX_DEPTH];
 #pragma unroll
       for (int q = 0; q < MAX_DEPTH; ++q) {
         be[q] = q < nb ? (R)C->beta[q] : (R)0;
-        dsrc[q] = (const R*)d.ring + (int64_t)(q < nb ? C->slot_b[q] : 0) * d.ring_stride;
+        dsrc[q] = gconst((const R*)d.ring) + (int64_t)(q < nb ? C->slot_b[q] : 0) * d.ring_stride;
       }
-      R* dw = (R*)d.ring + (int64_t)C->slot_w * d.ring_stride;
+      FM_GLOBAL R* dw = gmut((R*)d.ring) + (int64_t)C->slot_w * d.ring_stride;
+      FM_GLOBAL double* guf = gmut(d.uf);
       constexpr int UX = 4;
       for (int c = w; c < tl.ncol; c += WAVE_PENCILS)
         for (int eb = t; eb < outcnt; eb += UX * 64) {
@@ -517,7 +524,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
               for (int q = 0; q < MAX_DEPTH; ++q)
                 if (q < nb) a -= be[q] * dsrc[q][o];
               dl[u] = a;
-              uo[u] = d.uf[o];
+              uo[u] = guf[o];
             }
           }
 #pragma unroll
@@ -526,7 +533,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
             if (e < outcnt) {
               const int64_t o = (int64_t)(tl.p0b + c) * d.out_s1 + e;
               dw[o] = dl[u];
-              d.uf[o] = uo[u] + (double)dl[u];
+              guf[o] = uo[u] + (double)dl[u];
             }
           }
         }
@@ -545,7 +552,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
             if (eb + u * step < outcnt) tv[u] = sc[sidx<0>(c, eb + u * step, opitch)];
 #pragma unroll
           for (int u = 0; u < UD; ++u)
-            if (eb + u * step < outcnt) stc<R>(d.out, addr<0>(tl, c, eb + u * step, d.out_sa, d.out_s1), tv[u]);
+            if (eb + u * step < outcnt) stg<R>(gout, addr<0>(tl, c, eb + u * step, d.out_sa, d.out_s1), tv[u]);
         } else {
           R tv[UD];
 #pragma unroll
@@ -553,7 +560,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
             if (eb + u * step < outcnt) tv[u] = sr[sidx<0>(c, eb + u * step, opitch)];
 #pragma unroll
           for (int u = 0; u < UD; ++u)
-            if (eb + u * step < outcnt) ((R*)d.out)[addr<0>(tl, c, eb + u * step, d.out_sa, d.out_s1)] = tv[u];
+            if (eb + u * step < outcnt) gout[addr<0>(tl, c, eb + u * step, d.out_sa, d.out_s1)] = tv[u];
         }
       }
   }
