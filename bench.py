@@ -28,6 +28,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_polycrystal256.json")
+
+
+def kernel_source_hash():
+    """SHA-256 over the HIP sources, to tell whether stored counter readings
+    still describe the kernels that run."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2607_05929_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, size):
+    """HBM bytes per launch of `kernel` from the stored FETCH_SIZE / WRITE_SIZE
+    readings (each scaled by the reading of a plain 1 GiB copy), or None when
+    there are none for this workload or the kernels changed since."""
+    if size != 256 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash() or kernel not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel]
+    return 1024.0 * (k["fetch_KiB"] * t["fetch_factor"] + k["write_KiB"] * t["write_factor"])
 
 
 def kernel_bytes(prob, plan_geom, rbytes, n_d=1.0, n_b=0.0, n_gram=1.0):
@@ -182,6 +210,7 @@ def main():
                           n_b=aa_frac * (prob.aa_depth - 1), n_gram=prob.aa_depth)
     dom = max((k for k in prof if k in nbytes), key=lambda k: prof[k])
     achieved = nbytes[dom] / (prof[dom] * 1e-3) / 1e9
+    traffic = stored_traffic(dom, args.size)
     iter_ms = sum(prof.values())
     iter_bytes = sum(nbytes.values())
     p32.close()
@@ -222,7 +251,8 @@ def main():
                    "voxels": Nv, "iterations_per_solve": iters32 / args.steps,
                    "converged": conv32},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_GBs": (traffic / (prof[dom] * 1e-3) / 1e9) if traffic else None,
                      "algorithmic_bytes": nbytes[dom], "ms": prof[dom],
                      "iteration_ms": iter_ms, "iteration_bytes": iter_bytes,
                      "iteration_GBs": iter_bytes / (iter_ms * 1e-3) / 1e9,

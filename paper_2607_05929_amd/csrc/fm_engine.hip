@@ -168,7 +168,8 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
         // wavefront kernel staging (bounded as in build_group) must fit the LDS
         const int cols = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
         const size_t rows = (size_t)g.n[axis] + 3;
-        const size_t bytes = rows * (cols + 1) * 2 * (size_t)g.rbytes;
+        size_t bytes = rows * (cols + 1) * 2 * (size_t)g.rbytes;
+        if (E == 8) bytes += (size_t)WAVE_PENCILS * WT_SIZE * g.rbytes;
         if (bytes > 150 * 1024) g.wE[q][pass] = 0;
       }
       if (g.wE[q][pass]) g.cols[q][pass] = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
@@ -664,6 +665,7 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
           const int rows_out = mode == 0 ? M : d.n + 1;
           const size_t es_out = mode == 0 ? (d.cplx_out ? 2 * R : R) : (d.packed ? R : 2 * R);
           lds = std::max((size_t)(rows_in + 2) * (d.cols + 1) * es_in, (size_t)(rows_out + 2) * (d.cols + 1) * es_out);
+          if (E == 8) lds += (size_t)WAVE_PENCILS * WT_SIZE * R;   // transpose scratch
         } else {
           lds = (generic_radix(d.L) ? 2 : 1) * (size_t)d.F * pencil_stride(d.L) * 2 * R;
         }
@@ -909,6 +911,22 @@ int finish_step(fm_plan* p, const Ctrl& c, int t, bool last, fm_outputs* out, fm
   return 0;
 }
 
+// Iterations to enqueue before the next status read.  From the error decay
+// between two reads, the iterations still needed are estimated and three
+// quarters of them enqueued (at least one): the solve then rarely enqueues
+// iterations past convergence (those return at once, but cost launches),
+// at the price of a few more status reads near the end.  Without a usable
+// decay estimate the chunk doubles, up to 32.
+int next_chunk(const Ctrl& c, double e_prev, int m_prev, int chunk) {
+  if (e_prev > 0 && c.err > 0 && c.err < e_prev && c.m > m_prev && c.tol > 0) {
+    const double rate = std::pow(c.err / e_prev, 1.0 / (c.m - m_prev));
+    const double need = std::log(c.tol / c.err) / std::log(rate);
+    if (need > 0 && std::isfinite(need)) return std::max(1, std::min(64, (int)(0.75 * need)));
+    return 1;
+  }
+  return std::min(chunk * 2, 32);
+}
+
 int read_ctrl(fm_plan* p, Ctrl& c) {
   HIPCHK(hipMemcpyAsync(&c, dev_ctrl(p), sizeof(Ctrl), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
@@ -1052,13 +1070,17 @@ int fm_solve(fm_plan* p, const fm_load_step* steps, int32_t n_steps, fm_outputs*
     if (rc) return rc;
     Ctrl c;
     int chunk = 4;
+    double e_prev = -1.0;
+    int m_prev = 0;
     while (true) {
       rc = launch_iterations(*p->self, chunk);
       if (rc) return rc;
       rc = read_ctrl(p, c);
       if (rc) return rc;
       if (c.status != ST_RUNNING) break;
-      chunk = std::min(chunk * 2, 32);
+      chunk = next_chunk(c, e_prev, m_prev, chunk);
+      e_prev = c.err;
+      m_prev = c.m;
     }
     if (c.status == ST_MAXITER) result = FM_W_NOT_CONVERGED;
     rc = finish_step(p, c, t, t == n_steps - 1, out, log);

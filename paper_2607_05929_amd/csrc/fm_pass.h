@@ -266,11 +266,16 @@ __device__ __forceinline__ GreenCol<R> green_col(const PassDesc& d, int kx, int 
   return g;
 }
 
+// 1/x: the hardware reciprocal (1 ulp) in FP32, a correctly rounded
+// division in FP64.
+template <typename R> __device__ __forceinline__ R recip(R x) { return (R)1 / x; }
+template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename R>
 __device__ __forceinline__ R green_apply(const GreenCol<R>& g, int scheme, R s2, R c2, uint8_t f2) {
   const int npi = g.npi01 + ((f2 >> 1) & 1);
   const bool null = (g.z01 && (f2 & 1)) || (scheme == 0 ? npi >= 2 : npi == 3);
-  return null ? (R)0 : (R)1 / (g.A * c2 + g.B * s2);
+  return null ? (R)0 : recip<R>(g.A * c2 + g.B * s2);
 }
 
 template <typename R, int MODE, int XP>

@@ -52,18 +52,6 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* out) {
   }
 }
 
-// Extension of u_q at the low / high face of an axis: 1 symmetric, -1
-// anti-symmetric, 0 periodic.
-__device__ __forceinline__ int face_ext(int kind, int side) {
-  switch (kind) {
-    case K_DFT: return 0;
-    case K_DCT1: return 1;
-    case K_DST1: return -1;
-    case K_DCT3: return side == 0 ? 1 : -1;
-    default: return side == 0 ? -1 : 1;
-  }
-}
-
 __device__ __forceinline__ bool node_kept(int kind, int n, int j) {
   switch (kind) {
     case K_DFT: return j < n;

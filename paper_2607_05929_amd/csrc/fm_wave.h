@@ -168,20 +168,106 @@ __device__ __forceinline__ void wave_fft(cx<R> (&v)[E], const FM_GLOBAL cx<R>* W
   }
 }
 
-// Value of the partner position L - m of register k1, where lane t holds
-// m = k1 + E b with b = brev6(t): register E - k1 of lane 63 - t, or, for
-// k1 = 0, register 0 of lane brev6((64 - b) & 63).
-template <typename R, int E>
-__device__ __forceinline__ cx<R> mirror_val(const cx<R> (&v)[E], int k1, int lane0) {
-  const int t = threadIdx.x & 63;
-  cx<R> out = mk<R>(0, 0);
+// E = 8 (L = 512), the grids' common case: the 64-point DFT over the lanes
+// is split 8 x 8 through two in-wave transposes in LDS, so that every
+// butterfly is a radix-8 in registers (no lane exchanges, no idle half).
+// Lane t = a + 8 b = c + 8 k1; with n = a + 8 b + 64 j and
+// m = k1 + 8 c + 64 d,
+//   X[m] = sum_a W_8^{a d} W_64^{a c} sum_b W_8^{b c} W_512^{(a + 8 b) k1}
+//          sum_j W_8^{j k1} x[n].
+// Forward: lane t holds x[t + 64 j] in v[j]; on return lane t holds
+// X[(t >> 3) + 8 (t & 7) + 64 d] in v[d].  Inverse: the exact mirror image
+// (unnormalised).  The scratch of one wave is WT_SIZE reals; the two index
+// maps are conflict-free on the 64 LDS banks for both access orders.
+constexpr int WT_PITCH = 72, WT_SIZE = 8 * WT_PITCH;
+
+template <typename R, typename WI, typename RI>
+__device__ __forceinline__ void wave_xpose(R* sb, cx<R> (&v)[8], WI widx, RI ridx) {
+  R tmp[8];
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    // compile-time register selection: every lane takes the same register
-    const int want = (k1 == 0) ? 0 : E - k1;
-    if (q == want) out = shfl_c(v[q], k1 == 0 ? lane0 : 63 - t);
+  for (int part = 0; part < 2; ++part) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) sb[widx(r)] = part ? v[r].im : v[r].re;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int r = 0; r < 8; ++r) tmp[r] = sb[ridx(r)];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (part) v[r].im = tmp[r];
+      else v[r].re = tmp[r];
+    }
   }
-  return out;
+}
+
+template <typename R>
+__device__ __forceinline__ void wave_fft8(cx<R> (&v)[8], const FM_GLOBAL cx<R>* W, R* sb, bool inv) {
+  const int t = threadIdx.x & 63;
+  const int lo = t & 7, hi = t >> 3;
+  auto t1_w = [&](int r) { return WT_PITCH * r + t; };                  // lane a + 8 b, register k1
+  auto t1_r = [&](int r) { return WT_PITCH * hi + lo + 8 * r; };        // lane a + 8 k1, register b
+  auto t2_w = [&](int r) { return WT_PITCH * hi + 9 * r + lo; };        // lane a + 8 k1, register c
+  auto t2_r = [&](int r) { return WT_PITCH * hi + 9 * lo + r; };        // lane c + 8 k1, register a
+  const R sgn = inv ? (R)1 : (R)-1;
+  if (!inv) {
+    bfly8(v, sgn);                                                      // j -> k1
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) v[k1] = mul(v[k1], twid<R>(W, t * k1, false));
+    wave_xpose<R>(sb, v, t1_w, t1_r);
+    bfly8(v, sgn);                                                      // b -> c
+#pragma unroll
+    for (int c = 1; c < 8; ++c) v[c] = mul(v[c], twid<R>(W, 8 * lo * c, false));
+    wave_xpose<R>(sb, v, t2_w, t2_r);
+    bfly8(v, sgn);                                                      // a -> d
+  } else {
+    bfly8(v, sgn);                                                      // d -> a
+    wave_xpose<R>(sb, v, t2_r, t2_w);
+#pragma unroll
+    for (int c = 1; c < 8; ++c) v[c] = mul(v[c], twid<R>(W, 8 * lo * c, true));
+    bfly8(v, sgn);                                                      // c -> b
+    wave_xpose<R>(sb, v, t1_r, t1_w);
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) v[k1] = mul(v[k1], twid<R>(W, t * k1, true));
+    bfly8(v, sgn);                                                      // k1 -> j
+  }
+}
+
+// Spectral index held by register r of lane t after a forward transform.
+template <int E>
+__device__ __forceinline__ int spec_pos(int t, int r) {
+  if constexpr (E == 8) return (t >> 3) + 8 * (t & 7) + 64 * r;
+  else return r + E * brev6(t);
+}
+
+// Value of the partner position L - m of register r (lane t holds
+// m = spec_pos<E>(t, r)).  Lane exchange only; every lane takes part.
+//   E = 8: m = k1 + 8 c + 64 d (lane c + 8 k1) -> register 7 - d of the lane
+//          (7 - c) + 8 (8 - k1) for k1 > 0, (8 - c) for k1 = 0 < c; lane 0
+//          keeps its own register (8 - d) mod 8.
+//   else:  m = r + E b (b = brev6(t)) -> register E - r of lane 63 - t, or,
+//          for r = 0, register 0 of lane brev6((64 - b) & 63).
+template <typename R, int E>
+__device__ __forceinline__ cx<R> mirror_val(const cx<R> (&v)[E], int r, int lane0) {
+  const int t = threadIdx.x & 63;
+  if constexpr (E == 8) {
+    const int c = t & 7, k1 = t >> 3;
+    const int tp = k1 ? (7 - c) + 8 * (8 - k1) : ((8 - c) & 7);
+    const cx<R> o = shfl_c(v[7 - r], tp);
+    return t == 0 ? v[(8 - r) & 7] : o;
+  } else {
+    cx<R> out = mk<R>(0, 0);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      // compile-time register selection: every lane takes the same register
+      const int want = (r == 0) ? 0 : E - r;
+      if (q == want) out = shfl_c(v[q], r == 0 ? lane0 : 63 - t);
+    }
+    return out;
+  }
 }
 
 // Staging element access.  Strided tiles: row e holds the columns
@@ -216,9 +302,13 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   const FM_GLOBAL cx<R>* W = gconst((const cx<R>*)d.tw);
   const FM_GLOBAL R* gin = gconst((const R*)d.in);
   FM_GLOBAL R* gout = gmut((R*)d.out);
-  const LaneTw<R> ltw = lane_twiddles<R>(W, L);
-  R* sr = (R*)smem;            // staging, real elements (packed)
-  cx<R>* sc = (cx<R>*)smem;    // staging, complex elements
+  LaneTw<R> ltw;
+  if constexpr (E != 8) ltw = lane_twiddles<R>(W, L);
+  // E = 8: per-wave transpose scratch first, then the staging tile
+  R* wscr = (R*)smem + (E == 8 ? w * WT_SIZE : 0);
+  char* stage = smem + (E == 8 ? WAVE_PENCILS * WT_SIZE * sizeof(R) : 0);
+  R* sr = (R*)stage;           // staging, real elements (packed)
+  cx<R>* sc = (cx<R>*)stage;   // staging, complex elements
 
   if (MODE == 2 && threadIdx.x < cols)
     gcol[threadIdx.x] = green_col<R>(d, min(tl.p0b + (int)threadIdx.x, d.n_p0 - 1), tl.p1);
@@ -342,11 +432,12 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
       }
       v[j] = z;
     }
-    wave_fft<R, E>(v, W, ltw, false);
+    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, false);
+    else wave_fft<R, E>(v, W, ltw, false);
   } else {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int m = j + E * bt;    // inverse input layout: lane t, register j <-> X[j + E brev6(t)]
+      const int m = spec_pos<E>(t, j);   // inverse input layout: lane t, register j
       cx<R> z = mk<R>(0, 0);
       if (half) {
         // two Hermitian half spectra A (column ca) and B (column cb): Z = A + i B
@@ -365,7 +456,8 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
       }
       v[j] = z;
     }
-    wave_fft<R, E>(v, W, ltw, true);
+    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, true);
+    else wave_fft<R, E>(v, W, ltw, true);
   }
 
   if (MODE == 2) {
@@ -380,7 +472,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
       cx<R> nv[E];
 #pragma unroll
       for (int k1 = 0; k1 < E; ++k1) {
-        const int m = k1 + E * bt;
+        const int m = spec_pos<E>(t, k1);
         const cx<R> a = v[k1], b = conj(mirror_val<R, E>(v, k1, mlane0));
         const cx<R> A = scl(add(a, b), (R)0.5);
         const cx<R> Bv = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
@@ -396,7 +488,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
     } else {
 #pragma unroll
       for (int k1 = 0; k1 < E; ++k1) {
-        const int m = k1 + E * bt;
+        const int m = spec_pos<E>(t, k1);
         int k;
         R fr, fi;
         if (!spec_src<R>(kind, n, m, k, fr, fi)) { v[k1] = mk<R>(0, 0); continue; }
@@ -412,7 +504,8 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         }
       }
     }
-    wave_fft<R, E>(v, W, ltw, true);
+    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, true);
+    else wave_fft<R, E>(v, W, ltw, true);
   }
 
   // ---------------- phase C: registers -> staging ----------------
@@ -424,7 +517,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
     const int opitch = XP ? M + 1 : cols + 1;
 #pragma unroll
     for (int k1 = 0; k1 < E; ++k1) {
-      const int m = k1 + E * bt;
+      const int m = spec_pos<E>(t, k1);
       // coefficient index carried by position m (inverse of the Table 1 map)
       int k = -1;
       R fr = 1, fi = 0;

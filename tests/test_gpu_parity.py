@@ -126,6 +126,64 @@ def test_residual(B, prec, law, scheme):
     assert rel_err(macro, mref) < (1e-12 if prec == W.FP64 else 1e-5)
 
 
+def _bc_pattern(rng, pattern):
+    """Boundary codes [q][axis][side] for the multi-tile residual cases."""
+    bc = np.zeros((3, 3, 2), dtype=np.int32)
+    if pattern == "P":
+        return bc
+    if pattern in ("D", "N"):
+        bc[:] = W.D if pattern == "D" else W.N
+        return bc
+    for q in range(3):
+        for i in range(3):
+            if pattern == "mixwrap" and i == q:
+                continue                       # u_q periodic along axis q only
+            bc[q, i, 0] = rng.integers(1, 3)
+            bc[q, i, 1] = rng.integers(1, 3)
+    return bc
+
+
+# Grids spanning several stress-divergence tiles (31 x 7 node columns, 16
+# layers): ragged last tiles, a one-column tile (63 nodes), a one-layer
+# z chunk (17 nodes), one tile exactly (31 nodes).
+TILE_SHAPES = [(40, 17, 35), (62, 13, 33), (30, 6, 16)]
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32_MIXED])
+@pytest.mark.parametrize("pattern", ["P", "D", "N", "mix", "mixwrap"])
+@pytest.mark.parametrize("shape", TILE_SHAPES)
+def test_residual_tiles(B, prec, pattern, shape):
+    seed = zlib.crc32(f"{shape}{pattern}".encode())
+    rng = np.random.default_rng(seed)
+    scheme = W.TETRA2 if seed % 2 else W.HEX1
+    prob = W.random_small_problem(rng, n=shape, scheme=scheme, law="cubic",
+                                  bc=_bc_pattern(rng, pattern))
+    pl = osolver.Plan(prob)
+    uf = 1e-3 * rng.standard_normal((3,) + tuple(v + 1 for v in shape))
+    for q in range(3):
+        fd.zero_dismissed(uf[q], pl.exts[q])
+    step = prob.steps[0]
+    mats = MaterialSet(prob.materials, np.asarray(prob.mat_id).transpose(2, 1, 0))
+    state = mats.init_state(pl.nppv, pl.n)
+    gu = pl.grad(uf) + pl.grad(pl.ustar(step.c, step.G, step.H))
+    eps = 0.5 * (gu + np.swapaxes(gu, -1, -2))
+    sig, _ = mats.stress(eps, state, step.dt)
+    Dref = pl.div(sig)
+    gp = B.Plan(prob, prec=prec)
+    D, err, macro = gp.residual(zyx_nodes_from_xyz(uf), step)
+    gp.close()
+    D = xyz_nodes_from_zyx(D)
+    kept = np.stack(pl.kept)
+    e = rel_err(D[kept], Dref[kept])
+    ms = sig.mean(axis=(0, 1, 2, 3))
+    mref = np.array([ms[i, j] for (i, j) in osolver.VOIGT])
+    print(f"residual-tiles shape={shape} pattern={pattern} scheme={scheme} prec={prec} "
+          f"D err={e:.2e} macro err={rel_err(macro, mref):.2e}", flush=True)
+    assert np.all(D[~kept] == 0.0)
+    assert e < (1e-10 if prec == W.FP64 else 5e-5)
+    assert rel_err(macro, mref) < (1e-12 if prec == W.FP64 else 1e-5)
+
+
 @pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_small_solve_fp64(B, scheme, seed):
