@@ -604,6 +604,25 @@ int upload_tables(fm_plan* p) {
   return 0;
 }
 
+// Workgroups are dealt to the XCDs round robin (block b to XCD b mod 8).
+// Reorder a work list segment so that each XCD receives a contiguous run of
+// the spatial order: neighbouring tiles then share halos and partial cache
+// lines through the same L2.
+constexpr int N_XCD = 8;
+void xcd_order(std::vector<int2>& v, size_t begin, size_t end) {
+  const size_t T = end - begin;
+  if (T < 2 * N_XCD) return;
+  std::vector<int2> out(T);
+  size_t start[N_XCD];
+  size_t acc = 0;
+  for (int k = 0; k < N_XCD; ++k) {
+    start[k] = acc;
+    acc += T / N_XCD + ((size_t)k < T % N_XCD ? 1 : 0);
+  }
+  for (size_t b = 0; b < T; ++b) out[b] = v[begin + start[b % N_XCD] + b / N_XCD];
+  std::copy(out.begin(), out.end(), v.begin() + begin);
+}
+
 // Build a group's device arrays for `plans` inside [dev, dev+bytes).
 int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes, hipStream_t stream) {
   if (ns < 1) return fail(FM_E_INVALID_ARG, "empty group");
@@ -679,9 +698,11 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
       G.boff[k][b] = off;
       G.bn[k][b] = (int64_t)pb[k][b].size();
       pl[k].insert(pl[k].end(), pb[k][b].begin(), pb[k][b].end());
+      xcd_order(pl[k], (size_t)off, (size_t)(off + G.bn[k][b]));
       off += G.bn[k][b];
     }
   }
+  for (int k = 0; k < 3; ++k) xcd_order(wl[k], 0, wl[k].size());
   HIPCHK(hipMemcpyAsync(G.S, S.data(), sizeof(SolveDev) * ns, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(G.P, P.data(), sizeof(PassDesc) * ns * 15, hipMemcpyHostToDevice, stream));
   for (int k = 0; k < NWL; ++k) {

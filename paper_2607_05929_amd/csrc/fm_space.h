@@ -406,43 +406,50 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
   if (threadIdx.x < 8) gmut(s.part_s)[(int64_t)w.y * NPART_S + threadIdx.x] = outp[threadIdx.x];
 }
 
+// Gram matrix of the residual window, on Anderson steps only.  Dismissed
+// nodes hold D = 0, so every node enters without a mask.  Each thread takes
+// SPACE_TILE / 256 nodes and issues all of a component's loads before using
+// them; products are summed per thread in R, the block in FP64.
 template <typename R>
 __global__ void __launch_bounds__(256) k_gram(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
   const SolveDev& s = S[w.x];
-  const Ctrl* C = s.ctrl;
+  const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
   if (C->status != ST_RUNNING || !C->aa_pending) return;
-  double acc[NGRAM];
+  const int k = C->win_n;
+  constexpr int SUB = SPACE_TILE / 256;
+  const FM_GLOBAL R* slot[MAX_DEPTH];
+#pragma unroll
+  for (int a = 0; a < MAX_DEPTH; ++a)
+    slot[a] = gconst((const R*)s.Dring) + (int64_t)(a < k ? C->win_slot[a] : 0) * 3 * s.Nn;
+  R acc[NGRAM];
 #pragma unroll
   for (int i = 0; i < NGRAM; ++i) acc[i] = 0;
-  const int k = C->win_n;
-  for (int sub = 0; sub < SPACE_TILE / 256; ++sub) {
-  const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
-  if (v < s.Nn) {
-    const int N0 = s.N[0], N1 = s.N[1];
-    const int J[3] = {(int)(v % N0), (int)((v / N0) % N1), (int)(v / ((int64_t)N0 * N1))};
-    const R* ring = (const R*)s.Dring;
-    for (int q = 0; q < 3; ++q) {
-      bool kept = true;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) kept = kept && node_kept(s.kinds[q][i], s.n[i], J[i]);
-      if (!kept) continue;
-      double d[MAX_DEPTH];
+  for (int q = 0; q < 3; ++q) {
+    R d[SUB][MAX_DEPTH];
 #pragma unroll
-      for (int a = 0; a < MAX_DEPTH; ++a)
-        d[a] = a < k ? (double)ring[((int64_t)C->win_slot[a] * 3 + q) * s.Nn + v] : 0.0;
+    for (int sub = 0; sub < SUB; ++sub) {
+      const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
+#pragma unroll
+      for (int a = 0; a < MAX_DEPTH; ++a) d[sub][a] = (a < k && v < s.Nn) ? slot[a][q * s.Nn + v] : (R)0;
+    }
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub) {
       int t = 0;
 #pragma unroll
       for (int a = 0; a < MAX_DEPTH; ++a)
 #pragma unroll
-        for (int b = a; b < MAX_DEPTH; ++b) acc[t++] += d[a] * d[b];
+        for (int b = a; b < MAX_DEPTH; ++b) acc[t++] += d[sub][a] * d[sub][b];
     }
   }
-  }
   __shared__ double outp[NGRAM];
-  block_sum<NGRAM>(acc, outp);
+  double accd[NGRAM];
+#pragma unroll
+  for (int i = 0; i < NGRAM; ++i) accd[i] = (double)acc[i];
+  block_sum<NGRAM>(accd, outp);
   __syncthreads();
-  if (threadIdx.x < NGRAM) s.part_g[(int64_t)w.y * NGRAM + threadIdx.x] = outp[threadIdx.x];
+  if (threadIdx.x < NGRAM) gmut(s.part_g)[(int64_t)w.y * NGRAM + threadIdx.x] = outp[threadIdx.x];
 }
 
 // One block per solve.
