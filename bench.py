@@ -120,7 +120,7 @@ def cpu_baseline(seconds_hint=15.0):
     from oracle import solver as osolver
     nv = 64
     prob = W.config_polycrystal_bending(nv=nv, n_grains=8, seed=2)
-    prob.max_iter = 4
+    prob.max_iter = 30           # about 10-30 s of host time
     ru0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.time()
     r = osolver.solve(prob)
