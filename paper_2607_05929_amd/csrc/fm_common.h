@@ -63,7 +63,25 @@ struct Ctrl {
   double mixed_target[6];
   double dt, tol;
   double lam0, mu0;
+  // FP32 copies read as uniform scalars by the FP32 real-space kernel:
+  // G[9], H[27], tetrahedron cross terms hc[9] (h/2 H_{q,l',l''}, see k_sdiv)
+  float g32[9];
+  float h32[27];
+  float hc32[9];
+  int32_t pad2_;
 };
+
+// Refresh the FP32 copies of G, H and the TETRA2 cross terms (h_half = h/2
+// for TETRA2, 0 for HEX1).
+__host__ __device__ inline void ctrl_fp32_copies(Ctrl& c, double h_half) {
+  for (int i = 0; i < 9; ++i) c.g32[i] = (float)c.G[i];
+  for (int i = 0; i < 27; ++i) c.h32[i] = (float)c.H[i];
+  for (int q = 0; q < 3; ++q) {
+    c.hc32[0 * 3 + q] = (float)(h_half * c.H[(q * 3 + 1) * 3 + 2]);
+    c.hc32[1 * 3 + q] = (float)(h_half * c.H[(q * 3 + 0) * 3 + 2]);
+    c.hc32[2 * 3 + q] = (float)(h_half * c.H[(q * 3 + 0) * 3 + 1]);
+  }
+}
 
 struct LogEntry {
   double err;

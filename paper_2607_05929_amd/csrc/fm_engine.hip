@@ -348,9 +348,13 @@ int material_entry(const fm_material& mt, double* e /* MT_STRIDE */) {
       e[0] = mt.p[0]; e[1] = mt.p[1];
       return LAW_ISO;
     case FM_LAW_CUBIC: {
-      double R[3][3];
+      // packed upper triangle of the (symmetric) rotated Mandel stiffness
+      double R[3][3], full[36];
       quat_rot(mt.quat, R);
-      cubic_mandel(mt.p[0], mt.p[1], mt.p[2], R, e);
+      cubic_mandel(mt.p[0], mt.p[1], mt.p[2], R, full);
+      int k = 0;
+      for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) e[k++] = 0.5 * (full[i * 6 + j] + full[j * 6 + i]);
       return LAW_ANISO;
     }
     case FM_LAW_J2:
@@ -886,6 +890,7 @@ int begin_step(fm_plan* p, const fm_load_step& st, int t, const Ctrl* prev) {
         c.G[b * 3 + a] = prev->G[b * 3 + a];
       }
   }
+  ctrl_fp32_copies(c, p->d.scheme == FM_TETRA2 ? 0.5 * p->d.h : 0.0);
   HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, p->stream));
   return 0;
 }

@@ -4,7 +4,8 @@
 //
 // Material table entry (MT_STRIDE reals):
 //   ISO   : lambda, mu
-//   ANISO : C_M (6x6 Mandel stiffness, rotated cubic)
+//   ANISO : C_M (6x6 Mandel stiffness, rotated cubic), upper triangle packed
+//           row by row (21 reals)
 //   J2    : lambda, mu, sy0, H
 //   CP    : C_M (36) | S_M = C_M^-1 (36) | Schmid tensors P_M (12 x 6) |
 //           gdot0, n, tau0, taus, theta0
@@ -39,6 +40,24 @@ __device__ __forceinline__ void mat6(PT M, const R x[6], R y[6]) {
     R a = 0;
 #pragma unroll
     for (int j = 0; j < 6; ++j) a += M[i * 6 + j] * x[j];
+    y[i] = a;
+  }
+}
+
+// y = C x for a symmetric 6x6 matrix stored as its packed upper triangle.
+template <typename R, typename PT>
+__device__ __forceinline__ void mat6sym(PT Cp, const R x[6], R y[6]) {
+  R c[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) c[k] = Cp[k];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    R a = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      a += c[lo * 6 - lo * (lo - 1) / 2 + (hi - lo)] * x[j];
+    }
     y[i] = a;
   }
 }
@@ -196,7 +215,7 @@ __device__ __forceinline__ void law_elastic(int law, PT P, const R eps[6], R sig
   } else {
     R em[6], sm[6];
     to_mandel(eps, em);
-    mat6<R>(P, em, sm);
+    mat6sym<R>(P, em, sm);
     from_mandel(sm, sig);
   }
 #pragma unroll
@@ -218,7 +237,7 @@ __device__ __forceinline__ void law_eval(int law, PT P, const R eps[6], R sig[6]
   } else if (law == LAW_ANISO) {
     R em[6], sm[6];
     to_mandel(eps, em);
-    mat6<R>(P, em, sm);
+    mat6sym<R>(P, em, sm);
     from_mandel(sm, sig);
 #pragma unroll
     for (int i = 0; i < 7; ++i) stn[i] = st[i];

@@ -336,14 +336,31 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
   // per-thread partials in R (each thread sums at most 2 (SD_ZC + 1) points),
   // FP64 across the block
   R acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // u* gradient of this voxel column: gA + gB z_c.  FP32: from the uniform
+  // FP32 copies in the control block (gB and the cross terms stay scalar).
   R gA[3][3], gB[3][3], hc[3][3];
-  ustar_grad_column<R>(s, C, vx, vy, gA, gB);
-  tet_cross_terms<R>(s, C, hc);
+  if constexpr (sizeof(R) == 4) {
+    // read before any store, so that the uniform values can live in scalars
+    const float xc = (float)((vx + 0.5) * s.h), yc = (float)((vy + 0.5) * s.h);
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        gA[l][q] = C->g32[q * 3 + l] + C->h32[(q * 3 + l) * 3] * xc + C->h32[(q * 3 + l) * 3 + 1] * yc;
+        gB[l][q] = C->h32[(q * 3 + l) * 3 + 2];
+        hc[l][q] = C->hc32[l * 3 + q];
+      }
+  } else {
+    ustar_grad_column<R>(s, C, vx, vy, gA, gB);
+    tet_cross_terms<R>(s, C, hc);
+  }
   int mt_cur = mat[((int64_t)map_vox(Z0 - 1, n2, s.wrap[2]) * n1 + vy) * n0 + vx];
   for (int zl = Z0 - 1; zl < Z1; ++zl) {
     const int slot = (zl + 2) & 1;
     // material of the next voxel layer, fetched one layer ahead
-    const int mt_next = (zl + 1 < Z1) ? (int)mat[((int64_t)map_vox(zl + 1, n2, s.wrap[2]) * n1 + vy) * n0 + vx] : 0;
+    // (unconditional: the last layer reads a valid voxel it does not use, so the
+    // load needs no branch and its wait can sink to the end of the layer)
+    const uint16_t mt_next = mat[((int64_t)map_vox(zl + 1, n2, s.wrap[2]) * n1 + vy) * n0 + vx];
     {
       const int vz = map_vox(zl, n2, s.wrap[2]);
       const int law = gconst(s.mlaw)[mt_cur];
@@ -530,6 +547,7 @@ __global__ void __launch_bounds__(256) k_control(const SolveDev* __restrict__ S,
       if (i == j) C->G[i * 3 + i] += dE[p];
       else { C->G[i * 3 + j] += dE[p]; C->G[j * 3 + i] += dE[p]; }
     }
+    for (int i = 0; i < 9; ++i) C->g32[i] = (float)C->G[i];
   }
   const int depth = C->depth;
   const int wn = min(depth, m + 1);
