@@ -221,6 +221,14 @@ int fm_residual(fm_plan* plan, const fm_load_step* step, const double* d_uf, dou
 #define FM_N_KERNELS 9
 int fm_profile_iterations(fm_plan* plan, const fm_load_step* step, int32_t n_iter, double* ms);
 
+/* Launch mode of the iteration chunks of fm_solve, fm_batch_solve and the
+ * server (process-wide): enable != 0 (the default) enqueues each chunk of
+ * 1, 2, 4, ..., 32 iterations as one HIP graph, captured at first use per
+ * plan, batch or server group on a private stream and replayed on the
+ * caller's stream; 0 launches the nine kernels of every iteration directly.
+ * Results are identical in both modes.  Returns FM_OK. */
+int fm_set_graph_launch(int enable);
+
 /* Iterations performed by the last fm_solve / fm_batch_solve of this plan. */
 int64_t fm_plan_total_iterations(const fm_plan* plan);
 

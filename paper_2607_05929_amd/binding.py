@@ -100,6 +100,7 @@ EXPORTS = {
     "fm_server_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "fm_server_destroy": (None, [C.c_void_p]),
     "fm_last_error": (C.c_char_p, []),
+    "fm_set_graph_launch": (C.c_int, [C.c_int]),
 }
 
 _lib = None
@@ -334,6 +335,12 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def set_graph_launch(enable: bool):
+    """Process-wide launch mode of the iteration chunks: captured HIP graphs
+    (default) or direct kernel launches."""
+    check(lib().fm_set_graph_launch(1 if enable else 0), "fm_set_graph_launch")
 
 
 def solve(prob, prec=None, fields=True, log_capacity=0):

@@ -456,7 +456,28 @@ struct Group {
   int64_t bn[5][NBUCKET]{};     // items per bucket
   size_t blds[5][NBUCKET]{};    // dynamic LDS per bucket
   int* ids = nullptr;
+  // Captured iteration chunks of 1, 2, 4, ..., 32 iterations, replayed on
+  // `stream`; captured on a stream of their own, dropped when the group's
+  // device arrays are rebuilt.
+  static constexpr int NGRAPH = 6;
+  hipGraphExec_t graphs[NGRAPH] = {};
+  hipStream_t cap = nullptr;
+  Group() = default;
+  Group(const Group&) = delete;
+  Group& operator=(const Group&) = delete;
+  void drop_graphs() {
+    for (auto& g : graphs)
+      if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  }
+  ~Group() {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
+
+// Iteration chunks go through captured HIP graphs unless switched off
+// (fm_set_graph_launch).
+bool g_use_graphs = true;
 
 namespace {
 
@@ -630,6 +651,7 @@ void xcd_order(std::vector<int2>& v, size_t begin, size_t end) {
 // Build a group's device arrays for `plans` inside [dev, dev+bytes).
 int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes, hipStream_t stream) {
   if (ns < 1) return fail(FM_E_INVALID_ARG, "empty group");
+  G.drop_graphs();
   G.prec = plans[0]->d.prec;
   G.ns = ns;
   G.plastic = 0;
@@ -832,10 +854,46 @@ int launch_iteration(const Group& G) {
   return 0;
 }
 
-int launch_iterations(const Group& G, int count) {
+int launch_iterations_eager(const Group& G, int count) {
   for (int i = 0; i < count; ++i) {
     const int rc = G.prec == FM_FP64 ? launch_iteration<double>(G) : launch_iteration<float>(G);
     if (rc) return rc;
+  }
+  return 0;
+}
+
+// Capture `1 << idx` iterations of the group into an executable graph.
+int capture_chunk(Group& G, int idx) {
+  if (!G.cap) HIPCHK(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+  const hipStream_t user = G.stream;
+  G.stream = G.cap;
+  hipError_t e = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) { G.stream = user; return fail(FM_E_HIP, std::string("capture begin: ") + hipGetErrorString(e)); }
+  const int rc = launch_iterations_eager(G, 1 << idx);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(G.cap, &graph);
+  G.stream = user;
+  if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+  if (e != hipSuccess) return fail(FM_E_HIP, std::string("capture end: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&G.graphs[idx], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) { G.graphs[idx] = nullptr; return fail(FM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e)); }
+  return 0;
+}
+
+// Enqueue `count` iterations: as a sum of captured power-of-two chunks, or
+// eagerly (nine launches each) when graphs are switched off.
+int launch_iterations(Group& G, int count) {
+  if (!g_use_graphs) return launch_iterations_eager(G, count);
+  while (count > 0) {
+    int idx = 0;
+    while (idx + 1 < Group::NGRAPH && (2 << idx) <= count) ++idx;
+    if (!G.graphs[idx]) {
+      const int rc = capture_chunk(G, idx);
+      if (rc) return rc;
+    }
+    HIPCHK(hipGraphLaunch(G.graphs[idx], G.stream));
+    count -= 1 << idx;
   }
   return 0;
 }
@@ -967,6 +1025,11 @@ int read_ctrl(fm_plan* p, Ctrl& c) {
 extern "C" {
 
 const char* fm_last_error(void) { return g_err.c_str(); }
+
+int fm_set_graph_launch(int enable) {
+  g_use_graphs = enable != 0;
+  return FM_OK;
+}
 
 size_t fm_workspace_bytes(const fm_plan_desc* desc) {
   Geometry g;

@@ -172,3 +172,37 @@ def test_server_mix_equals_alone(B):
         np.testing.assert_array_equal(got["macro_sigma"], alone["macro_sigma"])
         assert got["iters"] == alone["iters"]
     srv.close()
+
+
+def test_graph_launch_equals_direct(B):
+    """Captured-graph iteration chunks reproduce direct launches bitwise:
+    one plan solved repeatedly (every chunk graph replayed many times, with
+    host reads and syncs between replays), both precisions, and a batch."""
+    rng = np.random.default_rng(77)
+    probs = [W.random_small_problem(rng, n=(9, 8, 7), scheme=s, law=law, tol=1e-9, n_steps=2)
+             for s, law in ((W.HEX1, "cubic"), (W.TETRA2, "j2"))]
+    try:
+        for prec in (W.FP64, W.FP32_MIXED):
+            for p in probs:
+                B.set_graph_launch(False)
+                ref = B.solve(p, prec=prec)
+                B.set_graph_launch(True)
+                plan = B.Plan(p, prec)
+                for rep in range(3):
+                    plan.reset()
+                    got = plan.solve()
+                    assert got["iters"] == ref["iters"], (rep, got["iters"], ref["iters"])
+                    np.testing.assert_array_equal(got["macro_sigma"], ref["macro_sigma"])
+                    np.testing.assert_array_equal(got["u"], ref["u"])
+                    np.testing.assert_array_equal(got["sig"], ref["sig"])
+                plan.close()
+        batch = _batch_problems()[:4]
+        B.set_graph_launch(False)
+        ref = B.batch_solve(batch)
+        B.set_graph_launch(True)
+        got = B.batch_solve(batch)
+        for a, b in zip(got, ref):
+            assert a["iters"] == b["iters"]
+            np.testing.assert_array_equal(a["macro_sigma"], b["macro_sigma"])
+    finally:
+        B.set_graph_launch(True)
