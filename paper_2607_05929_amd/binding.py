@@ -101,6 +101,8 @@ EXPORTS = {
     "fm_server_destroy": (None, [C.c_void_p]),
     "fm_last_error": (C.c_char_p, []),
     "fm_set_graph_launch": (C.c_int, [C.c_int]),
+    "fm_autotune": (C.c_int, [C.c_void_p, C.POINTER(LoadStep), C.c_int32, C.POINTER(C.c_int32),
+                              C.POINTER(C.c_double)]),
 }
 
 _lib = None
@@ -314,6 +316,16 @@ class Plan:
         check(lib().fm_profile_iterations(self.handle, load_steps([step]), n_iter, ms),
               "fm_profile_iterations")
         return dict(zip(self.KERNELS, list(ms)))
+
+    def autotune(self, step=None, n_iter=4):
+        """Pick the fastest transform kernel per axis pass (fm_autotune), then
+        reset the displacement.  Returns the choices and the timing table."""
+        step = self.prob.steps[0] if step is None else step
+        choice = (C.c_int32 * 5)()
+        ms = (C.c_double * 20)()
+        check(lib().fm_autotune(self.handle, load_steps([step]), n_iter, choice, ms), "fm_autotune")
+        self.reset()
+        return {"choice": list(choice), "ms": np.array(ms[:]).reshape(4, 5)}
 
     def reset(self, sync=True):
         """Zero the displacement and internal variables (same device-resident microstructure)."""

@@ -253,8 +253,13 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
     for (int a = 0; a < 3; ++a) L.tw_off[q][a] = take(2 * R * (size_t)g.L[q][a]);
   for (int q = 0; q < 3; ++q)
     for (int a = 0; a < 3; ++a) L.g_off[q][a] = take(17 * (size_t)g.M[q][a]);
+  // sized for the most tiles any transform-kernel choice can produce (one
+  // column per tile), so that fm_autotune can switch kernels in place
+  Geometry gmax = g;
+  for (int q = 0; q < 3; ++q)
+    for (int pass = 0; pass < 5; ++pass) gmax.cols[q][pass] = 1;
   int64_t t[NWL];
-  tiles_of(g, t);
+  tiles_of(gmax, t);
   L.group_bytes = group_bytes_for(1, t);
   L.group = take(L.group_bytes);
   L.total = o + ALIGN;   // slack for base alignment
@@ -1020,6 +1025,49 @@ int read_ctrl(fm_plan* p, Ctrl& c) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Transform-kernel autotuning
+// ---------------------------------------------------------------------------
+// Candidates for one pass index (all three components): 0 = wavefront kernel
+// (pencil length 64E), 1..3 = generic LDS kernel with F = Fmax, Fmax/2,
+// Fmax/4 transforms per block.  Returns false when the candidate does not
+// apply to some component (the pass then keeps its current kernel).
+constexpr int N_TUNE = 4;
+
+bool apply_choice(Geometry& g, int pass, int choice) {
+  Geometry h = g;
+  for (int q = 0; q < 3; ++q) {
+    const int axis = pass == 0 || pass == 4 ? 0 : (pass == 2 ? 2 : 1);
+    const int L = h.L[q][axis];
+    const bool packed = axis == 0 ? true : !h.cplx[q][axis - 1];
+    if (choice == 0) {
+      const int E = L % 64 == 0 ? L / 64 : 0;
+      if (!E || !wave_E_ok(E)) return false;
+      const int cols = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
+      size_t bytes = ((size_t)h.n[axis] + 3) * (cols + 1) * 2 * (size_t)h.rbytes;
+      if (E == 8) bytes += (size_t)WAVE_PENCILS * WT_SIZE * h.rbytes;
+      if (bytes > 150 * 1024) return false;
+      h.wE[q][pass] = E;
+      h.cols[q][pass] = cols;
+    } else {
+      const int Fmax = choose_F(L, h.rbytes, 16);
+      if ((Fmax >> (choice - 1)) < 1) return false;
+      const int F = Fmax >> (choice - 1);
+      if ((generic_radix(L) ? 2 : 1) * (size_t)F * pencil_stride(L) * 2 * h.rbytes > 160 * 1024 - 2048) return false;
+      h.wE[q][pass] = 0;
+      h.F[q][pass] = F;
+      h.cols[q][pass] = packed ? 2 * F : F;
+    }
+  }
+  g = h;
+  return true;
+}
+
+int rebuild_plan_group(fm_plan* p) {
+  fill_pass_descs(p);
+  return build_group(*p->self, &p, 1, p->ws + p->lay.group, p->lay.group_bytes, p->stream);
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1284,6 +1332,45 @@ int fm_profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, 
   HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   return FM_OK;
+}
+
+int fm_autotune(fm_plan* p, const fm_load_step* step, int32_t n_iter, int32_t* choice, double* ms) {
+  if (!p || !step || n_iter < 1) return fail(FM_E_INVALID_ARG, "null argument");
+  if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called first");
+  const Geometry saved = p->g;
+  int best[5];
+  double best_ms[5];
+  for (int pass = 0; pass < 5; ++pass) {
+    best[pass] = -1;
+    best_ms[pass] = 1e300;
+  }
+  double tms[FM_N_KERNELS];
+  for (int c = 0; c < N_TUNE; ++c) {
+    Geometry g2 = saved;
+    bool valid[5], any = false;
+    for (int pass = 0; pass < 5; ++pass) any |= (valid[pass] = apply_choice(g2, pass, c));
+    for (int pass = 0; pass < 5; ++pass)
+      if (ms) ms[c * 5 + pass] = -1.0;
+    if (!any) continue;
+    p->g = g2;
+    int rc = rebuild_plan_group(p);
+    if (rc) { p->g = saved; rebuild_plan_group(p); return rc; }
+    rc = fm_profile_iterations(p, step, n_iter, tms);
+    if (rc) { p->g = saved; rebuild_plan_group(p); return rc; }
+    for (int pass = 0; pass < 5; ++pass) {
+      if (!valid[pass]) continue;
+      const double t = tms[4 + pass];
+      if (ms) ms[c * 5 + pass] = t;
+      if (t < best_ms[pass]) { best_ms[pass] = t; best[pass] = c; }
+    }
+  }
+  Geometry g = saved;
+  for (int pass = 0; pass < 5; ++pass) {
+    if (best[pass] >= 0) apply_choice(g, pass, best[pass]);
+    if (choice) choice[pass] = best[pass];
+  }
+  p->g = g;
+  return rebuild_plan_group(p);
 }
 
 }  // extern "C"

@@ -206,3 +206,23 @@ def test_graph_launch_equals_direct(B):
             np.testing.assert_array_equal(a["macro_sigma"], b["macro_sigma"])
     finally:
         B.set_graph_launch(True)
+
+
+def test_autotune_then_solve_matches_oracle(B, inclusion32):
+    """fm_autotune times every applicable transform kernel per axis pass and
+    keeps the fastest; the tuned plan still reproduces the oracle."""
+    prob, ref = inclusion32
+    plan = B.Plan(prob, W.FP64)
+    info = plan.autotune(n_iter=3)
+    print(f"autotune choice {info['choice']}\n{info['ms']}", flush=True)
+    assert all(c >= 0 for c in info["choice"])
+    for pass_, c in enumerate(info["choice"]):
+        t = info["ms"][c, pass_]
+        assert t > 0 and t <= info["ms"][:, pass_][info["ms"][:, pass_] > 0].min() + 1e-12
+    r = plan.solve()
+    plan.close()
+    assert all(r["converged"])
+    e = rel_err(r["macro_sigma"], ref["macro_sigma"])
+    es = rel_err(r["sig"], ref["sig"])
+    print(f"autotuned inclusion32 macro err {e:.2e} sigma err {es:.2e}", flush=True)
+    assert e < 1e-7 and es < 1e-6
