@@ -135,6 +135,32 @@ def cpu_baseline(seconds_hint=15.0):
                       f"incl. setup, {wall:.1f} s wall, {os.cpu_count()} host cpus visible"}
 
 
+def serving_sample(B, W, count=12, rate=200.0, sizes=(32, 48), n_steps=10, arena_gib=24):
+    """Continuous batching of a Poisson stream of crystal-plasticity
+    torsion-bending solves (FP32-mixed) through the server API, in real time:
+    latency from arrival to completion (queueing included)."""
+    reqs = W.serving_stream(count=count, rate=rate, sizes=sizes, n_steps=n_steps, prec=W.FP32_MIXED)
+    srv = B.Server(arena_bytes=arena_gib << 30, max_active=64)
+    t0 = time.time()
+    tickets, k = [], 0
+    while True:
+        now = time.time() - t0
+        while k < len(reqs) and reqs[k].arrival_s <= now:
+            tickets.append(srv.submit(reqs[k].problem, arrival_s=reqs[k].arrival_s, now_s=now))
+            k += 1
+        srv.step(4, time.time() - t0)
+        if k == len(reqs) and all(srv.poll(t)[0] == 2 for t in tickets):
+            break
+    wall = time.time() - t0
+    st = srv.stats()
+    srv.close()
+    return {"requests": count, "rate_req_s": rate, "sizes": list(sizes), "increments": n_steps,
+            "law": "FCC crystal plasticity, TETRA2, tol 1e-6", "completed": st["completed"],
+            "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+            "mean_latency_s": st["mean_latency_s"], "wall_s": wall,
+            "throughput_voxel_iter_s": st["voxel_iters"] / wall, "arena_peak_bytes": st["arena_peak"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +169,7 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
                     help="run a 1 GiB device copy (torch) first: a plain copy kernel of known size "
                          "used to scale the FETCH_SIZE / WRITE_SIZE counters, and its bandwidth")
@@ -232,6 +259,12 @@ def main():
         p64.close()
         log(f"FP64: {it64} iterations in {t64:.3f} s; <sigma> FP32 vs FP64 rel diff {rel:.2e}")
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_sample(B, W)
+        log(f"serving: {serving['completed']} requests, p50 {serving['p50_latency_s']:.3f} s, "
+            f"p99 {serving['p99_latency_s']:.3f} s, {serving['throughput_voxel_iter_s']:.3e} voxel-iter/s")
+
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     out = {
         "metric": "voxel-iter/s (FP32-mixed, macro-stress parity vs FP64)",
@@ -260,6 +293,7 @@ def main():
         "copy_GBs": copy_gbs,
         "fp64": fp64,
         "speedup_fp32_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -63,6 +63,7 @@ struct Geometry {
   int cols[3][5];    // columns (or rows) per block per pass
   int wrap[3];       // axis periodic for some component (halo voxels take the periodic image)
   int sd_nt[3];      // fused stress-divergence tiles per axis
+  int sd_zc;         // node layers per fused stress-divergence tile
   int ntile_s;       // fused stress-divergence tiles
   int ntile_v;       // voxel tiles (commit)
   int ntile_d;       // node tiles (Gram matrix)
@@ -185,7 +186,14 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   }
   g.sd_nt[0] = (int)cdiv(g.N[0], SD_TX);
   g.sd_nt[1] = (int)cdiv(g.N[1], SD_TY);
-  g.sd_nt[2] = (int)cdiv(g.N[2], SD_ZC);
+  // Layers per tile: SD_ZC, halved while the grid gives fewer than 8 blocks
+  // per compute unit (32 for the plastic laws, whose per-layer cost is high):
+  // each tile recomputes one voxel layer below it, so fewer layers cost more
+  // law evaluations but fill the GPU on small grids.
+  const int64_t want = (d->with_state ? 32 : 8) * 256;
+  g.sd_zc = SD_ZC;
+  while (g.sd_zc > 1 && (int64_t)g.sd_nt[0] * g.sd_nt[1] * cdiv(g.N[2], g.sd_zc) < want) g.sd_zc /= 2;
+  g.sd_nt[2] = (int)cdiv(g.N[2], g.sd_zc);
   g.ntile_s = g.sd_nt[0] * g.sd_nt[1] * g.sd_nt[2];
   g.ntile_v = (int)cdiv(g.Nv, SPACE_TILE);
   g.ntile_d = (int)cdiv(g.Nn, SPACE_TILE);
@@ -1129,6 +1137,7 @@ int fm_plan_create(const fm_plan_desc* desc, void* d_workspace, size_t ws_bytes,
   s.mixed_wrap = 0;
   for (int i = 0; i < 3; ++i) {
     s.sd_nt[i] = g.sd_nt[i];
+    s.sd_zc = g.sd_zc;
     s.wrap[i] = g.wrap[i];
     for (int q = 0; q < 3; ++q)
       if (g.wrap[i] && g.kinds[q][i] != K_DFT) s.mixed_wrap = 1;

@@ -70,7 +70,8 @@ __device__ __forceinline__ R powabs(R r, R n) {
 }
 
 // Backward-Euler FCC crystal viscoplasticity (Newton on sigma_M, dGamma with
-// backtracking, started from the elastic predictor scaled to |tau|/tau_c <= 2).
+// backtracking, started from the elastic predictor scaled to |tau|/tau_c <= 2;
+// stops at the tolerance or when no backtracked step lowers the residual).
 template <typename R, typename PT>
 __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[6], R epm[6], R& Gout) {
   const PT Cm = P;
@@ -178,14 +179,19 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
     }
     R lam = 1;
     R s_new[6], d_new, Rs2[6], Rg2, gd2[12], tc2, nr2 = nr;
+    bool improved = false;
     for (int ls = 0; ls < 30; ++ls) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) s_new[i] = sig[i] - lam * dx[i];
       d_new = fmax(dG - lam * dx[6], (R)0);
       nr2 = resid(s_new, d_new, Rs2, Rg2, gd2, tc2);
-      if (nr2 < nr || lam < (R)1e-7) break;
+      if (nr2 < nr) { improved = true; break; }
+      if (lam < (R)1e-7) break;
       lam *= (R)0.5;
     }
+    // No step decreases the residual: the iterate sits at the rounding floor
+    // of R; keep it (further Newton steps would only repeat the search).
+    if (!improved) break;
 #pragma unroll
     for (int i = 0; i < 6; ++i) { sig[i] = s_new[i]; Rs[i] = Rs2[i]; }
     dG = d_new; Rg = Rg2; tc = tc2; nr = nr2;

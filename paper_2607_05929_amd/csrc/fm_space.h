@@ -219,7 +219,9 @@ __global__ void __launch_bounds__(256) k_commit(const SolveDev* __restrict__ S, 
 // ---------------------------------------------------------------------------
 // Fused stress + divergence of one iteration.
 //
-// A block owns a tile of SD_TX x SD_TY node columns and SD_ZC node layers.
+// A block owns a tile of SD_TX x SD_TY node columns and sd_zc node layers
+// (at most SD_ZC; fewer on small grids and for the costly plastic laws, so
+// that there are enough blocks to fill the GPU).
 // It marches up the layers: for voxel layer z it evaluates the behaviour law
 // on the 32 x 8 voxels that touch the tile (one per thread, the tile plus a
 // one-voxel halo) into an LDS ring of two voxel layers, then forms the
@@ -321,8 +323,8 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
   extern __shared__ __align__(16) char smem[];
   R* sl = (R*)smem;                                    // [2 layers][12][SD_VT]
   const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
-  const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * SD_ZC;
-  const int Z1 = min(Z0 + SD_ZC, s.N[2]);
+  const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * s.sd_zc;
+  const int Z1 = min(Z0 + s.sd_zc, s.N[2]);
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
   const int n0 = s.n[0], n1 = s.n[1], n2 = s.n[2];
   const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
@@ -333,7 +335,7 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
   const bool has_node = lx < SD_TX && ly < SD_TY && J0 < s.N[0] && J1 < s.N[1];
   const FM_GLOBAL uint16_t* mat = gconst(s.mat);
   const R wip = (R)1 / (R)s.nppv;
-  // per-thread partials in R (each thread sums at most 2 (SD_ZC + 1) points),
+  // per-thread partials in R (each thread sums at most 2 (sd_zc + 1) points),
   // FP64 across the block
   R acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // u* gradient of this voxel column: gA + gB z_c.  FP32: from the uniform
