@@ -164,7 +164,9 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
       const int L = g.L[q][axis];
       const bool packed = axis == 0 ? true : !g.cplx[q][axis - 1];
       const int E = L % 64 == 0 ? L / 64 : 0;
-      g.wE[q][pass] = (E && wave_E_ok(E)) ? E : 0;
+      // wavefront kernels address a component's buffers with 32-bit byte offsets
+      const int64_t comp_bytes = std::max(std::max(g.s1[q], g.s2[q]) * (int64_t)g.rbytes, g.Nn * (int64_t)8);
+      g.wE[q][pass] = (E && wave_E_ok(E) && comp_bytes < ((int64_t)1 << 32)) ? E : 0;
       if (g.wE[q][pass]) {
         // wavefront kernel staging (bounded as in build_group) must fit the LDS
         const int cols = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
@@ -449,12 +451,16 @@ struct fm_plan {
 };
 
 // A set of solves advanced together.
-constexpr int NBUCKET = 10;   // pass kernel variants: generic + wavefront E = 1,2,3,4,5,6,8,12,16
-inline int bucket_of_E(int E) {
+// Pass kernel variants: generic (0), wavefront E = 1,2,3,4,5,6,12,16 (1-9,
+// 7 unused), and for E = 8 one bucket per transform kind and packing
+// (10 + 2 kind + packed), whose kernels fix both at compile time.
+constexpr int NBUCKET = 20;
+inline int bucket_of(int E, int kind, int packed) {
   switch (E) { case 1: return 1; case 2: return 2; case 3: return 3; case 4: return 4; case 5: return 5;
-               case 6: return 6; case 8: return 7; case 12: return 8; case 16: return 9; default: return 0; }
+               case 6: return 6; case 8: return 10 + 2 * kind + (packed ? 1 : 0); case 12: return 8;
+               case 16: return 9; default: return 0; }
 }
-constexpr int E_of_bucket[NBUCKET] = {0, 1, 2, 3, 4, 5, 6, 8, 12, 16};
+constexpr int E_of_bucket[NBUCKET] = {0, 1, 2, 3, 4, 5, 6, 8, 12, 16, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8};
 
 struct Group {
   int prec = 0;
@@ -707,7 +713,9 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
         const int64_t ntiles = pass == 0 || pass == 4 ? d.tiles_p0 : (int64_t)d.tiles_p0 * d.n_p1;
         const int pk = pass == 0 ? 0 : pass == 1 ? 1 : pass == 2 ? 2 : pass == 3 ? 3 : 4;   // launch order slot
         const int E = p->g.wE[q][pass];
-        const int b = bucket_of_E(E);
+        const int b = bucket_of(E, d.kind, d.packed);
+        if (E == 8 && (d.cols != (d.packed ? 2 * WAVE_PENCILS : WAVE_PENCILS) || d.L != 512))
+          return fail(FM_E_INVALID_ARG, "internal: wavefront pass descriptor does not match its kernel");
         for (int64_t ty = 0; ty < ntiles; ++ty) pb[pk][b].push_back(make_int2(di, (int)ty));
         size_t lds;
         const size_t R = p->g.rbytes;
@@ -755,14 +763,43 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   return 0;
 }
 
+template <typename R, int MODE, int XP, int KIND>
+hipError_t set_w8_lds(int big) {
+  hipError_t r = hipFuncSetAttribute((const void*)k_wave<R, MODE, XP, 8, KIND, 1>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (r) return r;
+  if constexpr (!XP)
+    r = hipFuncSetAttribute((const void*)k_wave<R, MODE, XP, 8, KIND, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  return r;
+}
+
+template <typename R, int MODE, int XP>
+hipError_t set_w8_lds_kinds(int big) {
+  hipError_t r;
+  if ((r = set_w8_lds<R, MODE, XP, K_DFT>(big))) return r;
+  if ((r = set_w8_lds<R, MODE, XP, K_DCT1>(big))) return r;
+  if ((r = set_w8_lds<R, MODE, XP, K_DST1>(big))) return r;
+  if ((r = set_w8_lds<R, MODE, XP, K_DCT3>(big))) return r;
+  return set_w8_lds<R, MODE, XP, K_DST3>(big);
+}
+
 template <typename R, int E>
 hipError_t set_wave_lds(int big) {
-  hipError_t r;
-  if ((r = hipFuncSetAttribute((const void*)k_wave<R, 0, 1, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
-  if ((r = hipFuncSetAttribute((const void*)k_wave<R, 1, 1, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
-  if ((r = hipFuncSetAttribute((const void*)k_wave<R, 0, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
-  if ((r = hipFuncSetAttribute((const void*)k_wave<R, 1, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
-  return hipFuncSetAttribute((const void*)k_wave<R, 2, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if constexpr (E == 8) {
+    hipError_t r;
+    if ((r = set_w8_lds_kinds<R, 0, 1>(big))) return r;
+    if ((r = set_w8_lds_kinds<R, 1, 1>(big))) return r;
+    if ((r = set_w8_lds_kinds<R, 0, 0>(big))) return r;
+    if ((r = set_w8_lds_kinds<R, 1, 0>(big))) return r;
+    return set_w8_lds_kinds<R, 2, 0>(big);
+  } else {
+    hipError_t r;
+    if ((r = hipFuncSetAttribute((const void*)k_wave<R, 0, 1, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+    if ((r = hipFuncSetAttribute((const void*)k_wave<R, 1, 1, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+    if ((r = hipFuncSetAttribute((const void*)k_wave<R, 0, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+    if ((r = hipFuncSetAttribute((const void*)k_wave<R, 1, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+    return hipFuncSetAttribute((const void*)k_wave<R, 2, 0, E>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  }
 }
 
 template <typename R>
@@ -792,13 +829,36 @@ int set_lds_limits() {
   return 0;
 }
 
+// E = 8 kernels specialised on kind and packing (x passes are always packed;
+// the fused z pass only runs strided).
+template <typename R, int MODE, int XP, int KIND>
+void launch_w8(int packed, dim3 grid, size_t lds, hipStream_t st, const PassDesc* P, const int2* wl,
+               const SolveDev* S) {
+  if (packed) hipLaunchKernelGGL((k_wave<R, MODE, XP, 8, KIND, 1>), grid, dim3(WAVE_THREADS), lds, st, P, wl, S);
+  else if constexpr (!XP) hipLaunchKernelGGL((k_wave<R, MODE, XP, 8, KIND, 0>), grid, dim3(WAVE_THREADS), lds, st, P, wl, S);
+}
+
+template <typename R, int MODE, int XP>
+void launch_w8_kind(int kind, int packed, dim3 grid, size_t lds, hipStream_t st, const PassDesc* P,
+                    const int2* wl, const SolveDev* S) {
+  switch (kind) {
+    case K_DFT: launch_w8<R, MODE, XP, K_DFT>(packed, grid, lds, st, P, wl, S); break;
+    case K_DCT1: launch_w8<R, MODE, XP, K_DCT1>(packed, grid, lds, st, P, wl, S); break;
+    case K_DST1: launch_w8<R, MODE, XP, K_DST1>(packed, grid, lds, st, P, wl, S); break;
+    case K_DCT3: launch_w8<R, MODE, XP, K_DCT3>(packed, grid, lds, st, P, wl, S); break;
+    default: launch_w8<R, MODE, XP, K_DST3>(packed, grid, lds, st, P, wl, S); break;
+  }
+}
+
 template <typename R, int MODE, int XP>
 int launch_bucket(const Group& G, int pk, int b) {
   const int2* wl = G.wl[2 + pk] + G.boff[pk][b];
   const dim3 grid((unsigned)G.bn[pk][b]);
   const size_t lds = G.blds[pk][b];
   hipStream_t st = G.stream;
-  switch (E_of_bucket[b]) {
+  if (b >= 10) {
+    launch_w8_kind<R, MODE, XP>((b - 10) >> 1, (b - 10) & 1, grid, lds, st, G.P, wl, G.S);
+  } else switch (E_of_bucket[b]) {
     case 0: hipLaunchKernelGGL((k_pass<R, MODE, XP>), grid, dim3(PASS_THREADS), lds, st, G.P, wl, G.S); break;
     case 1: hipLaunchKernelGGL((k_wave<R, MODE, XP, 1>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
     case 2: hipLaunchKernelGGL((k_wave<R, MODE, XP, 2>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
@@ -806,7 +866,6 @@ int launch_bucket(const Group& G, int pk, int b) {
     case 4: hipLaunchKernelGGL((k_wave<R, MODE, XP, 4>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
     case 5: hipLaunchKernelGGL((k_wave<R, MODE, XP, 5>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
     case 6: hipLaunchKernelGGL((k_wave<R, MODE, XP, 6>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
-    case 8: hipLaunchKernelGGL((k_wave<R, MODE, XP, 8>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
     case 12: hipLaunchKernelGGL((k_wave<R, MODE, XP, 12>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
     default: hipLaunchKernelGGL((k_wave<R, MODE, XP, 16>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
   }
@@ -1050,6 +1109,7 @@ bool apply_choice(Geometry& g, int pass, int choice) {
     if (choice == 0) {
       const int E = L % 64 == 0 ? L / 64 : 0;
       if (!E || !wave_E_ok(E)) return false;
+      if (std::max(std::max(h.s1[q], h.s2[q]) * (int64_t)h.rbytes, h.Nn * (int64_t)8) >= ((int64_t)1 << 32)) return false;
       const int cols = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
       size_t bytes = ((size_t)h.n[axis] + 3) * (cols + 1) * 2 * (size_t)h.rbytes;
       if (E == 8) bytes += (size_t)WAVE_PENCILS * WT_SIZE * h.rbytes;

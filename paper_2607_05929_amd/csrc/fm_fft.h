@@ -28,23 +28,33 @@ template <typename R> __device__ __forceinline__ cx<R> twid(const cx<R>* W, int 
   cx<R> w = W[t];
   return inv ? conj(w) : w;   // forward uses the table value exp(-2 pi i t / L)
 }
-// Complex element idx of an interleaved global array, one 2-wide access.
+// Global loads and stores at a 32-bit byte offset from a wavefront-uniform
+// base: the address is the scalar base plus one zero-extended VGPR, with no
+// 64-bit arithmetic per access.  Complex values move as one 2-wide access.
+template <typename T>
+__device__ __forceinline__ T gld(const FM_GLOBAL char* base, uint32_t off) {
+  return *(const FM_GLOBAL T*)(base + off);
+}
+template <typename T>
+__device__ __forceinline__ void gst(FM_GLOBAL char* base, uint32_t off, T v) {
+  *(FM_GLOBAL T*)(base + off) = v;
+}
 template <typename R>
-__device__ __forceinline__ cx<R> ldg(const FM_GLOBAL R* base, int64_t idx) {
+__device__ __forceinline__ cx<R> gldc(const FM_GLOBAL char* base, uint32_t off) {
   typedef R R2 __attribute__((ext_vector_type(2)));
-  const R2 v = *(const FM_GLOBAL R2*)(base + 2 * idx);
+  const R2 v = gld<R2>(base, off);
   return mk<R>(v.x, v.y);
 }
 template <typename R>
-__device__ __forceinline__ void stg(FM_GLOBAL R* base, int64_t idx, cx<R> c) {
+__device__ __forceinline__ void gstc(FM_GLOBAL char* base, uint32_t off, cx<R> c) {
   typedef R R2 __attribute__((ext_vector_type(2)));
   R2 v;
   v.x = c.re; v.y = c.im;
-  *(FM_GLOBAL R2*)(base + 2 * idx) = v;
+  gst<R2>(base, off, v);
 }
 
 template <typename R> __device__ __forceinline__ cx<R> twid(const FM_GLOBAL cx<R>* W, int t, bool inv) {
-  const cx<R> w = ldg<R>((const FM_GLOBAL R*)W, t);
+  const cx<R> w = gldc<R>((const FM_GLOBAL char*)W, (uint32_t)t * (uint32_t)sizeof(cx<R>));
   return inv ? conj(w) : w;
 }
 
@@ -196,6 +206,11 @@ __host__ __device__ inline int n_freq(int kind, int n) {
     case K_DST1: return n - 1;
     default: return n;
   }
+}
+
+// Extension factor S_f of a kind (L = S_f n).
+__host__ __device__ constexpr int kind_sf(int kind) {
+  return kind == K_DFT ? 1 : ((kind == K_DCT1 || kind == K_DST1) ? 2 : 4);
 }
 
 __host__ __device__ inline int ext_len(int kind, int n) {

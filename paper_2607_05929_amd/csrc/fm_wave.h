@@ -277,21 +277,36 @@ __device__ __forceinline__ int sidx(int c, int e, int pitch) {
   return XP ? c * pitch + e : e * pitch + c;
 }
 
-template <typename R, int MODE, int XP, int E>
+// KIND >= 0 fixes the transform kind and PK the packing (1: two real
+// columns per pencil, 0: one complex column) at compile time, and with them
+// the axis length (n = L / S_f), the tile width, the element types and every
+// staging pitch; KIND = -1 reads them from the descriptor.  Global accesses
+// use 32-bit byte offsets from a per-block base: the plan keeps each
+// component's buffers below 4 GiB for these kernels.
+template <typename R, int MODE, int XP, int E, int KIND = -1, int PK = -1>
 __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restrict__ descs,
                                                        const int2* __restrict__ work,
                                                        const SolveDev* __restrict__ S) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ GreenCol<R> gcol[32];
+  __shared__ GreenCol<R> gcol[2 * WAVE_PENCILS];
   const int2 wk = work[blockIdx.x];
   const PassDesc& d = descs[wk.x];
   const FM_GLOBAL Ctrl* C = gconst(S[d.solve].ctrl);
   if (C->status != ST_RUNNING) return;
   constexpr int L = 64 * E;
-  const int n = d.n, kind = d.kind;
-  const int cols = d.cols;                      // 32 packed real or 16 complex
-  const bool packed = d.packed;
+  constexpr bool SK = KIND >= 0;
+  const int kind = SK ? KIND : d.kind;
+  const int n = SK ? L / kind_sf(KIND) : d.n;
+  const bool packed = SK ? PK == 1 : d.packed != 0;
+  const int lcols = packed ? 4 : 3;             // tile width: 16 real or 8 complex columns
+  const int cols = 1 << lcols;
   const bool half = packed && kind == K_DFT;
+  // complex elements in and out (real DTT data travels packed as reals)
+  const bool cin = SK ? (MODE == 1 ? (PK != 1 || KIND == K_DFT) : PK != 1) : d.cplx_in != 0;
+  const bool cout_ = SK ? (MODE == 0 ? (PK != 1 || KIND == K_DFT) : PK != 1)
+                        : (MODE == 0 ? d.cplx_out != 0 : !packed);
+  const uint32_t esi = cin ? 2 * sizeof(R) : sizeof(R);
+  const uint32_t eso = cout_ ? 2 * sizeof(R) : sizeof(R);
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
   const int bt = brev6(t);                      // spectral lane order
   const int mlane0 = brev6((64 - bt) & 63);     // lane of the partner of register 0
@@ -300,8 +315,9 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   else { tl.p0b = (wk.y % d.tiles_p0) * cols; tl.p1 = wk.y / d.tiles_p0; }
   tl.ncol = min(cols, d.n_p0 - tl.p0b);
   const FM_GLOBAL cx<R>* W = gconst((const cx<R>*)d.tw);
-  const FM_GLOBAL R* gin = gconst((const R*)d.in);
-  FM_GLOBAL R* gout = gmut((R*)d.out);
+  // first element of the block's tile, in elements of the input / output
+  const int64_t in_blk = XP ? (int64_t)tl.p0b * d.in_s1 : (int64_t)tl.p1 * d.in_s1 + tl.p0b;
+  const int64_t out_blk = XP ? (int64_t)tl.p0b * d.out_s1 : (int64_t)tl.p1 * d.out_s1 + tl.p0b;
   LaneTw<R> ltw;
   if constexpr (E != 8) ltw = lane_twiddles<R>(W, L);
   // E = 8: per-wave transpose scratch first, then the staging tile
@@ -315,84 +331,97 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
 
   // ---------------- phase A: tile -> staging (coalesced) ----------------
   int j0 = 0, cnt;
-  if (MODE == 1) cnt = d.len_in;
+  if (MODE == 1) cnt = SK ? (half ? n / 2 + 1 : n_freq(kind, n)) : d.len_in;
   else raw_range(kind, n, j0, cnt);
-  const bool cin = d.cplx_in;
   const int pitch = XP ? cnt + 1 : cols + 1;
   {
-    const int nd = (XP && MODE == 0) ? C->n_d : 0;
-    R al[MAX_DEPTH];
-    const FM_GLOBAL R* src[MAX_DEPTH];
-    if (XP && MODE == 0) {
-#pragma unroll
-      for (int q = 0; q < MAX_DEPTH; ++q) {
-        al[q] = q < nd ? (R)C->alpha[q] : (R)0;
-        src[q] = gconst((const R*)d.ring) + (int64_t)(q < nd ? C->slot_d[q] : 0) * d.ring_stride;
-      }
-    }
     // Loads are issued in batches of U per thread before any is written to
     // the staging array, so that U requests per lane are in flight at once.
     constexpr int U = 8;
     if (XP) {
-      for (int c = w; c < cols; c += WAVE_PENCILS) {
-        const bool okc = c < tl.ncol;
-        for (int eb = t; eb < cnt; eb += U * 64) {
-          if (MODE == 0) {
+      const int s1 = (int)d.in_s1;
+      if (MODE == 0) {
+        // x forward: Green input x = sum_q alpha_q D_{slot q} (Anderson mix)
+        const int nd = C->n_d;
+        R al[MAX_DEPTH];
+        const FM_GLOBAL char* src[MAX_DEPTH];
+#pragma unroll
+        for (int q = 0; q < MAX_DEPTH; ++q) {
+          al[q] = q < nd ? (R)C->alpha[q] : (R)0;
+          src[q] = (const FM_GLOBAL char*)gconst((const R*)d.ring) +
+                   ((int64_t)(q < nd ? C->slot_d[q] : 0) * d.ring_stride + in_blk) * (int64_t)sizeof(R);
+        }
+        for (int c = w; c < cols; c += WAVE_PENCILS) {
+          const bool okc = c < tl.ncol;
+          const uint32_t rowe = (uint32_t)(c * s1 + j0);
+          for (int eb = t; eb < cnt; eb += U * 64) {
             R tv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
               const int e = eb + 64 * u;
               tv[u] = 0;
               if (okc && e < cnt) {
-                const int64_t o = addr<1>(tl, c, j0 + e, 0, d.in_s1);
-                R a = al[0] * src[0][o];
+                const uint32_t o = (rowe + (uint32_t)e) * (uint32_t)sizeof(R);
+                R a = al[0] * gld<R>(src[0], o);
 #pragma unroll
                 for (int q = 1; q < MAX_DEPTH; ++q)
-                  if (q < nd) a += al[q] * src[q][o];
+                  if (q < nd) a += al[q] * gld<R>(src[q], o);
                 tv[u] = a;
               }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
               if (eb + 64 * u < cnt) sr[sidx<1>(c, eb + 64 * u, pitch)] = tv[u];
-          } else if (cin) {
-            cx<R> tv[U];
+          }
+        }
+      } else {
+        const FM_GLOBAL char* gin = (const FM_GLOBAL char*)gconst((const char*)d.in) + in_blk * (int64_t)esi;
+        for (int c = w; c < cols; c += WAVE_PENCILS) {
+          const bool okc = c < tl.ncol;
+          const uint32_t rowe = (uint32_t)(c * s1 + j0);
+          for (int eb = t; eb < cnt; eb += U * 64) {
+            if (cin) {
+              cx<R> tv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const int e = eb + 64 * u;
-              tv[u] = mk<R>(0, 0);
-              if (okc && e < cnt) tv[u] = ldg<R>(gin, addr<1>(tl, c, j0 + e, 0, d.in_s1));
+              for (int u = 0; u < U; ++u) {
+                const int e = eb + 64 * u;
+                tv[u] = mk<R>(0, 0);
+                if (okc && e < cnt) tv[u] = gldc<R>(gin, (rowe + (uint32_t)e) * esi);
+              }
+#pragma unroll
+              for (int u = 0; u < U; ++u)
+                if (eb + 64 * u < cnt) sc[sidx<1>(c, eb + 64 * u, pitch)] = tv[u];
+            } else {
+              R tv[U];
+#pragma unroll
+              for (int u = 0; u < U; ++u) {
+                const int e = eb + 64 * u;
+                tv[u] = 0;
+                if (okc && e < cnt) tv[u] = gld<R>(gin, (rowe + (uint32_t)e) * esi);
+              }
+#pragma unroll
+              for (int u = 0; u < U; ++u)
+                if (eb + 64 * u < cnt) sr[sidx<1>(c, eb + 64 * u, pitch)] = tv[u];
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-              if (eb + 64 * u < cnt) sc[sidx<1>(c, eb + 64 * u, pitch)] = tv[u];
-          } else {
-            R tv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const int e = eb + 64 * u;
-              tv[u] = 0;
-              if (okc && e < cnt) tv[u] = gin[addr<1>(tl, c, j0 + e, 0, d.in_s1)];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-              if (eb + 64 * u < cnt) sr[sidx<1>(c, eb + 64 * u, pitch)] = tv[u];
           }
         }
       }
     } else {
-      const int rows_per = 64 / cols;          // 2 (packed) or 4 (complex) rows per wavefront
-      const int c = t % cols;
+      const FM_GLOBAL char* gin = (const FM_GLOBAL char*)gconst((const char*)d.in) + in_blk * (int64_t)esi;
+      const int rows_per = 64 >> lcols;          // 4 (packed) or 8 (complex) rows per wavefront
+      const int c = t & (cols - 1);
       const int step = WAVE_PENCILS * rows_per;
       const bool okc = c < tl.ncol;
-      for (int eb = w * rows_per + t / cols; eb < cnt; eb += U * step) {
+      const int e0 = w * rows_per + (t >> lcols);
+      const uint32_t ostep = (uint32_t)step * (uint32_t)d.in_sa * esi;
+      uint32_t o = ((uint32_t)c + (uint32_t)(j0 + e0) * (uint32_t)d.in_sa) * esi;
+      for (int eb = e0; eb < cnt; eb += U * step, o += U * ostep) {
         if (cin) {
           cx<R> tv[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int e = eb + u * step;
             tv[u] = mk<R>(0, 0);
-            if (okc && e < cnt) tv[u] = ldg<R>(gin, addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1));
+            if (okc && eb + u * step < cnt) tv[u] = gldc<R>(gin, o + u * ostep);
           }
 #pragma unroll
           for (int u = 0; u < U; ++u)
@@ -401,9 +430,8 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
           R tv[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int e = eb + u * step;
             tv[u] = 0;
-            if (okc && e < cnt) tv[u] = gin[addr<0>(tl, c, j0 + e, d.in_sa, d.in_s1)];
+            if (okc && eb + u * step < cnt) tv[u] = gld<R>(gin, o + u * ostep);
           }
 #pragma unroll
           for (int u = 0; u < U; ++u)
@@ -462,10 +490,10 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
 
   if (MODE == 2) {
     // Green operator on the spectrum held in registers (lane t, register k1:
-    // position m = k1 + E brev6(t)); same structure-preserving scaling as the
+    // position m = spec_pos(t, k1)); same structure-preserving scaling as the
     // generic pass.
-    const FM_GLOBAL double* zs2 = gconst(d.gs2[2]);
-    const FM_GLOBAL double* zc2 = gconst(d.gc2[2]);
+    const FM_GLOBAL char* zs2 = (const FM_GLOBAL char*)gconst(d.gs2[2]);
+    const FM_GLOBAL char* zc2 = (const FM_GLOBAL char*)gconst(d.gc2[2]);
     const FM_GLOBAL uint8_t* zfl = gconst(d.gfl[2]);
     const bool okA = ca < tl.ncol, okB = packed ? cb < tl.ncol : false;
     if (half) {
@@ -477,7 +505,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         const cx<R> A = scl(add(a, b), (R)0.5);
         const cx<R> Bv = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
         const int mk_ = m <= n / 2 ? m : n - m;
-        const R s2 = (R)zs2[mk_], c2 = (R)zc2[mk_];
+        const R s2 = (R)gld<double>(zs2, 8u * mk_), c2 = (R)gld<double>(zc2, 8u * mk_);
         const uint8_t fl = zfl[mk_];
         const R fa = okA ? green_apply<R>(gcol[ca], d.scheme, s2, c2, fl) : (R)0;
         const R fb = okB ? green_apply<R>(gcol[cb], d.scheme, s2, c2, fl) : (R)0;
@@ -492,7 +520,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         int k;
         R fr, fi;
         if (!spec_src<R>(kind, n, m, k, fr, fi)) { v[k1] = mk<R>(0, 0); continue; }
-        const R s2 = (R)zs2[k], c2 = (R)zc2[k];
+        const R s2 = (R)gld<double>(zs2, 8u * k), c2 = (R)gld<double>(zc2, 8u * k);
         const uint8_t fl = zfl[k];
         if (packed) {
           const R fa = okA ? green_apply<R>(gcol[ca], d.scheme, s2, c2, fl) : (R)0;
@@ -565,12 +593,14 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   __syncthreads();
 
   // ---------------- phase D: staging -> memory (coalesced) ----------------
-  const bool cout_ = (MODE == 0) ? d.cplx_out : !packed;
   constexpr int UD = 8;
   if (XP) {
     const int opitch = outcnt + 1;
+    const int s1 = (int)d.out_s1;
     if (MODE == 0) {
-      for (int c = w; c < tl.ncol; c += WAVE_PENCILS)
+      FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) + out_blk * (int64_t)eso;
+      for (int c = w; c < tl.ncol; c += WAVE_PENCILS) {
+        const uint32_t rowe = (uint32_t)(c * s1);
         for (int eb = t; eb < outcnt; eb += UD * 64) {
           if (cout_) {
             cx<R> tv[UD];
@@ -579,7 +609,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
               if (eb + 64 * u < outcnt) tv[u] = sc[sidx<1>(c, eb + 64 * u, opitch)];
 #pragma unroll
             for (int u = 0; u < UD; ++u)
-              if (eb + 64 * u < outcnt) stg<R>(gout, addr<1>(tl, c, eb + 64 * u, d.out_sa, d.out_s1), tv[u]);
+              if (eb + 64 * u < outcnt) gstc<R>(gout, (rowe + (uint32_t)(eb + 64 * u)) * eso, tv[u]);
           } else {
             R tv[UD];
 #pragma unroll
@@ -587,23 +617,27 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
               if (eb + 64 * u < outcnt) tv[u] = sr[sidx<1>(c, eb + 64 * u, opitch)];
 #pragma unroll
             for (int u = 0; u < UD; ++u)
-              if (eb + 64 * u < outcnt) gout[addr<1>(tl, c, eb + 64 * u, d.out_sa, d.out_s1)] = tv[u];
+              if (eb + 64 * u < outcnt) gst<R>(gout, (rowe + (uint32_t)(eb + 64 * u)) * eso, tv[u]);
           }
         }
+      }
     } else {
       // x inverse: u^f += w - sum_k beta_k delta_k, new increment into the ring
       const int nb = C->n_b;
       R be[MAX_DEPTH];
-      const FM_GLOBAL R* dsrc[MAX_DEPTH];
+      const FM_GLOBAL char* dsrc[MAX_DEPTH];
+      const FM_GLOBAL char* ring = (const FM_GLOBAL char*)gconst((const R*)d.ring);
 #pragma unroll
       for (int q = 0; q < MAX_DEPTH; ++q) {
         be[q] = q < nb ? (R)C->beta[q] : (R)0;
-        dsrc[q] = gconst((const R*)d.ring) + (int64_t)(q < nb ? C->slot_b[q] : 0) * d.ring_stride;
+        dsrc[q] = ring + ((int64_t)(q < nb ? C->slot_b[q] : 0) * d.ring_stride + out_blk) * (int64_t)sizeof(R);
       }
-      FM_GLOBAL R* dw = gmut((R*)d.ring) + (int64_t)C->slot_w * d.ring_stride;
-      FM_GLOBAL double* guf = gmut(d.uf);
+      FM_GLOBAL char* dw = (FM_GLOBAL char*)gmut((R*)d.ring) +
+                           ((int64_t)C->slot_w * d.ring_stride + out_blk) * (int64_t)sizeof(R);
+      FM_GLOBAL char* guf = (FM_GLOBAL char*)gmut(d.uf) + out_blk * (int64_t)sizeof(double);
       constexpr int UX = 4;
-      for (int c = w; c < tl.ncol; c += WAVE_PENCILS)
+      for (int c = w; c < tl.ncol; c += WAVE_PENCILS) {
+        const uint32_t rowe = (uint32_t)(c * s1);
         for (int eb = t; eb < outcnt; eb += UX * 64) {
           R dl[UX];
           double uo[UX];
@@ -611,33 +645,38 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
           for (int u = 0; u < UX; ++u) {
             const int e = eb + 64 * u;
             if (e < outcnt) {
-              const int64_t o = (int64_t)(tl.p0b + c) * d.out_s1 + e;
+              const uint32_t o = rowe + (uint32_t)e;
               R a = sr[sidx<1>(c, e, opitch)];
 #pragma unroll
               for (int q = 0; q < MAX_DEPTH; ++q)
-                if (q < nb) a -= be[q] * dsrc[q][o];
+                if (q < nb) a -= be[q] * gld<R>(dsrc[q], o * (uint32_t)sizeof(R));
               dl[u] = a;
-              uo[u] = guf[o];
+              uo[u] = gld<double>(guf, o * 8u);
             }
           }
 #pragma unroll
           for (int u = 0; u < UX; ++u) {
             const int e = eb + 64 * u;
             if (e < outcnt) {
-              const int64_t o = (int64_t)(tl.p0b + c) * d.out_s1 + e;
-              dw[o] = dl[u];
-              guf[o] = uo[u] + (double)dl[u];
+              const uint32_t o = rowe + (uint32_t)e;
+              gst<R>(dw, o * (uint32_t)sizeof(R), dl[u]);
+              gst<double>(guf, o * 8u, uo[u] + (double)dl[u]);
             }
           }
         }
+      }
     }
   } else {
+    FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) + out_blk * (int64_t)eso;
     const int opitch = cols + 1;
-    const int rows_per = 64 / cols;
+    const int rows_per = 64 >> lcols;
     const int step = WAVE_PENCILS * rows_per;
-    const int c = t % cols;
+    const int c = t & (cols - 1);
+    const int e0 = w * rows_per + (t >> lcols);
+    const uint32_t ostep = (uint32_t)step * (uint32_t)d.out_sa * eso;
+    uint32_t o = ((uint32_t)c + (uint32_t)e0 * (uint32_t)d.out_sa) * eso;
     if (c < tl.ncol)
-      for (int eb = w * rows_per + t / cols; eb < outcnt; eb += UD * step) {
+      for (int eb = e0; eb < outcnt; eb += UD * step, o += UD * ostep) {
         if (cout_) {
           cx<R> tv[UD];
 #pragma unroll
@@ -645,7 +684,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
             if (eb + u * step < outcnt) tv[u] = sc[sidx<0>(c, eb + u * step, opitch)];
 #pragma unroll
           for (int u = 0; u < UD; ++u)
-            if (eb + u * step < outcnt) stg<R>(gout, addr<0>(tl, c, eb + u * step, d.out_sa, d.out_s1), tv[u]);
+            if (eb + u * step < outcnt) gstc<R>(gout, o + u * ostep, tv[u]);
         } else {
           R tv[UD];
 #pragma unroll
@@ -653,7 +692,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
             if (eb + u * step < outcnt) tv[u] = sr[sidx<0>(c, eb + u * step, opitch)];
 #pragma unroll
           for (int u = 0; u < UD; ++u)
-            if (eb + u * step < outcnt) gout[addr<0>(tl, c, eb + u * step, d.out_sa, d.out_s1)] = tv[u];
+            if (eb + u * step < outcnt) gst<R>(gout, o + u * ostep, tv[u]);
         }
       }
   }
