@@ -237,19 +237,15 @@ __device__ __forceinline__ int64_t addr(const Tile& t, int c, int e, int64_t sa,
 
 // Per-column Green data of the fused z pass: den(kz) = A cos^2(xi_z/2) +
 // B sin^2(xi_z/2) (the modified-frequency products of Eqs. NSGO2_* are
-// linear in the z factors), plus the x-y part of the null-mode test.
+// linear in the z factors).
 template <typename R>
 struct GreenCol {
   R A, B;
-  int z01, npi01;
 };
 
 template <typename R>
 __device__ __forceinline__ GreenCol<R> green_col(const PassDesc& d, int kx, int ky) {
   GreenCol<R> g;
-  const uint8_t f0 = d.gfl[0][kx], f1 = d.gfl[1][ky];
-  g.z01 = (f0 & f1) & 1;
-  g.npi01 = ((f0 >> 1) & 1) + ((f1 >> 1) & 1);
   const double s0 = d.gs2[0][kx], c0 = d.gc2[0][kx], s1 = d.gs2[1][ky], c1 = d.gc2[1][ky];
   double a[3], b[3];
   if (d.scheme == 0) {
@@ -271,11 +267,16 @@ __device__ __forceinline__ GreenCol<R> green_col(const PassDesc& d, int kx, int 
 template <typename R> __device__ __forceinline__ R recip(R x) { return (R)1 / x; }
 template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Green factor 1/den, 0 on the null modes.  The null modes (decided in index
+// space: all three frequencies at 0; two or more at pi for HEX1, all three
+// for TETRA2) are exactly the zeros of den: the 1D tables hold exact 0 and 1
+// at the index-flagged frequencies and values strictly inside (0, 1)
+// elsewhere, and den is a sum of non-negative products of them, each term
+// vanishing only through a flagged factor.  So den == 0 is the index rule.
 template <typename R>
-__device__ __forceinline__ R green_apply(const GreenCol<R>& g, int scheme, R s2, R c2, uint8_t f2) {
-  const int npi = g.npi01 + ((f2 >> 1) & 1);
-  const bool null = (g.z01 && (f2 & 1)) || (scheme == 0 ? npi >= 2 : npi == 3);
-  return null ? (R)0 : recip<R>(g.A * c2 + g.B * s2);
+__device__ __forceinline__ R green_apply(const GreenCol<R>& g, R s2, R c2) {
+  const R den = g.A * c2 + g.B * s2;
+  return den == (R)0 ? (R)0 : recip<R>(den);
 }
 
 template <typename R, int MODE, int XP>
@@ -404,7 +405,6 @@ __global__ void __launch_bounds__(PASS_THREADS) k_pass(const PassDesc* __restric
     // r2c columns: positions m and n-m are separated, scaled and recombined.
     const double* zs2 = d.gs2[2];
     const double* zc2 = d.gc2[2];
-    const uint8_t* zfl = d.gfl[2];
     if (half) {
       const int npair = n / 2 + 1;
       for (int idx = threadIdx.x; idx < F * npair; idx += nthr) {
@@ -416,9 +416,8 @@ __global__ void __launch_bounds__(PASS_THREADS) k_pass(const PassDesc* __restric
         const cx<R> B = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
         const int c0 = 2 * f, c1 = 2 * f + 1;
         const R s2 = (R)zs2[m], c2 = (R)zc2[m];
-        const uint8_t fl = zfl[m];
-        const R fa = (c0 < t.ncol) ? green_apply<R>(gcol[c0], d.scheme, s2, c2, fl) : (R)0;
-        const R fb = (c1 < t.ncol) ? green_apply<R>(gcol[c1], d.scheme, s2, c2, fl) : (R)0;
+        const R fa = (c0 < t.ncol) ? green_apply<R>(gcol[c0], s2, c2) : (R)0;
+        const R fb = (c1 < t.ncol) ? green_apply<R>(gcol[c1], s2, c2) : (R)0;
         const cx<R> A2 = scl(A, fa), B2 = scl(B, fb);
         Z[PD(m)] = mk<R>(A2.re - B2.im, A2.im + B2.re);
         if (mm != m) {
@@ -434,15 +433,14 @@ __global__ void __launch_bounds__(PASS_THREADS) k_pass(const PassDesc* __restric
         R fr, fi;
         if (!spec_src<R>(kind, n, m, k, fr, fi)) { Z[PD(m)] = mk<R>(0, 0); continue; }
         const R s2 = (R)zs2[k], c2 = (R)zc2[k];
-        const uint8_t fl = zfl[k];
         if (packed) {
           const int c0 = 2 * f, c1 = 2 * f + 1;
-          const R fa = (c0 < t.ncol) ? green_apply<R>(gcol[c0], d.scheme, s2, c2, fl) : (R)0;
-          const R fb = (c1 < t.ncol) ? green_apply<R>(gcol[c1], d.scheme, s2, c2, fl) : (R)0;
+          const R fa = (c0 < t.ncol) ? green_apply<R>(gcol[c0], s2, c2) : (R)0;
+          const R fb = (c1 < t.ncol) ? green_apply<R>(gcol[c1], s2, c2) : (R)0;
           const cx<R> z = Z[PD(m)];
           Z[PD(m)] = (fi == (R)0) ? mk<R>(z.re * fa, z.im * fb) : mk<R>(z.re * fb, z.im * fa);
         } else {
-          const R g = (f < t.ncol) ? green_apply<R>(gcol[f], d.scheme, s2, c2, fl) : (R)0;
+          const R g = (f < t.ncol) ? green_apply<R>(gcol[f], s2, c2) : (R)0;
           Z[PD(m)] = scl(Z[PD(m)], g);
         }
       }

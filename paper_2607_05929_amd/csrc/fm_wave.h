@@ -292,9 +292,24 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   const int2 wk = work[blockIdx.x];
   const PassDesc& d = descs[wk.x];
   const FM_GLOBAL Ctrl* C = gconst(S[d.solve].ctrl);
-  if (C->status != ST_RUNNING) return;
+  // Only the x forward pass needs the control block to address its inputs
+  // (Anderson weights and slots); the others issue their tile loads first
+  // and test the solve's status after them, so that the dependent loads of
+  // descriptor, control pointer and status do not delay the data.  A stopped
+  // solve's buffers stay allocated, and nothing is written for it.
+  constexpr bool CTRL_FIRST = MODE == 0 && XP;
+  if (CTRL_FIRST && C->status != ST_RUNNING) return;
   constexpr int L = 64 * E;
   constexpr bool SK = KIND >= 0;
+  // rows loaded by the strided passes when the kind is fixed, and the
+  // loads per thread that cover them in one batch
+  constexpr int NC = SK ? L / kind_sf(KIND) : 0;
+  constexpr int CNT_IN = !SK ? 0
+                         : (MODE == 1 && PK == 1 && KIND == K_DFT) ? NC / 2 + 1
+                         : KIND == K_DCT1 ? NC + 1 : KIND == K_DST1 ? NC - 1 : NC;
+  constexpr int CNT_OUT = !SK ? 0 : MODE != 0 ? NC + 1 : (PK == 1 && KIND == K_DFT) ? NC / 2 + 1
+                          : KIND == K_DCT1 ? NC + 1 : KIND == K_DST1 ? NC - 1 : NC;
+  constexpr int STEP_C = WAVE_PENCILS * (PK == 1 ? 4 : 8);
   const int kind = SK ? KIND : d.kind;
   const int n = SK ? L / kind_sf(KIND) : d.n;
   const bool packed = SK ? PK == 1 : d.packed != 0;
@@ -337,7 +352,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   {
     // Loads are issued in batches of U per thread before any is written to
     // the staging array, so that U requests per lane are in flight at once.
-    constexpr int U = 8;
+    constexpr int U = SK && !XP ? (CNT_IN + STEP_C - 1) / STEP_C : 8;
     if (XP) {
       const int s1 = (int)d.in_s1;
       if (MODE == 0) {
@@ -441,6 +456,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
     }
   }
   __syncthreads();
+  if (!CTRL_FIRST && C->status != ST_RUNNING) return;
 
   // ---------------- phase B: pencil -> registers, FFT ----------------
   cx<R> v[E];
@@ -494,7 +510,6 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
     // generic pass.
     const FM_GLOBAL char* zs2 = (const FM_GLOBAL char*)gconst(d.gs2[2]);
     const FM_GLOBAL char* zc2 = (const FM_GLOBAL char*)gconst(d.gc2[2]);
-    const FM_GLOBAL uint8_t* zfl = gconst(d.gfl[2]);
     const bool okA = ca < tl.ncol, okB = packed ? cb < tl.ncol : false;
     if (half) {
       cx<R> nv[E];
@@ -506,9 +521,8 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         const cx<R> Bv = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
         const int mk_ = m <= n / 2 ? m : n - m;
         const R s2 = (R)gld<double>(zs2, 8u * mk_), c2 = (R)gld<double>(zc2, 8u * mk_);
-        const uint8_t fl = zfl[mk_];
-        const R fa = okA ? green_apply<R>(gcol[ca], d.scheme, s2, c2, fl) : (R)0;
-        const R fb = okB ? green_apply<R>(gcol[cb], d.scheme, s2, c2, fl) : (R)0;
+        const R fa = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
+        const R fb = okB ? green_apply<R>(gcol[cb], s2, c2) : (R)0;
         nv[k1] = mk<R>(fa * A.re - fb * Bv.im, fa * A.im + fb * Bv.re);
       }
 #pragma unroll
@@ -521,13 +535,12 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
         R fr, fi;
         if (!spec_src<R>(kind, n, m, k, fr, fi)) { v[k1] = mk<R>(0, 0); continue; }
         const R s2 = (R)gld<double>(zs2, 8u * k), c2 = (R)gld<double>(zc2, 8u * k);
-        const uint8_t fl = zfl[k];
         if (packed) {
-          const R fa = okA ? green_apply<R>(gcol[ca], d.scheme, s2, c2, fl) : (R)0;
-          const R fb = okB ? green_apply<R>(gcol[cb], d.scheme, s2, c2, fl) : (R)0;
+          const R fa = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
+          const R fb = okB ? green_apply<R>(gcol[cb], s2, c2) : (R)0;
           v[k1] = (fi == (R)0) ? mk<R>(v[k1].re * fa, v[k1].im * fb) : mk<R>(v[k1].re * fb, v[k1].im * fa);
         } else {
-          const R g = okA ? green_apply<R>(gcol[ca], d.scheme, s2, c2, fl) : (R)0;
+          const R g = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
           v[k1] = scl(v[k1], g);
         }
       }
@@ -593,7 +606,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   __syncthreads();
 
   // ---------------- phase D: staging -> memory (coalesced) ----------------
-  constexpr int UD = 8;
+  constexpr int UD = SK && !XP ? (CNT_OUT + STEP_C - 1) / STEP_C : 8;
   if (XP) {
     const int opitch = outcnt + 1;
     const int s1 = (int)d.out_s1;
