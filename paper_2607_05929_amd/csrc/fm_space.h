@@ -242,77 +242,113 @@ __device__ __forceinline__ int map_vox(int g, int n, int wrap) {
   return g;
 }
 
-// Divergence at node J from the two voxel layers of the ring.  Faces: a
-// node kept for component q sits on a reflecting face of q only where u_q is
-// symmetric (an anti-symmetric face dismisses the node), and there each
-// mirror corner contributes exactly what its in-grid image contributes (the
-// T1/T2 exchange and the signs of Eq. Continuous_der_symmetry_per cancel the
-// flipped stencil sign).  So the mirror corners are dropped and the sum is
-// doubled per reflecting face.  Mirror corners are dropped through halo
-// slots holding zero (axes periodic for no component) or, on axes periodic
-// for another component, through a per-corner mask; periodic components
-// read their halo slot (the periodic image voxel) as in the interior.
-// Mask bits of mirror corners to drop on axes periodic for another
-// component: bit (q * 6 + 2 * i + b) set when corner side b of axis i is
-// outside the grid at this node and u_q is not periodic along i.
-__device__ __forceinline__ int drop_bits(const SolveDev& s, const int J[3]) {
-  int m = 0;
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      if (s.wrap[i] && s.kinds[q][i] != K_DFT) {
-        if (J[i] == 0) m |= 1 << (q * 6 + 2 * i);
-        if (J[i] == s.n[i]) m |= 1 << (q * 6 + 2 * i + 1);
-      }
-  return m;
-}
-
+// Faces: a node kept for component q sits on a reflecting face of q only
+// where u_q is symmetric (an anti-symmetric face dismisses the node), and
+// there each mirror corner contributes exactly what its in-grid image
+// contributes (the T1/T2 exchange and the signs of Eq.
+// Continuous_der_symmetry_per cancel the flipped stencil sign).  So the
+// mirror corners are dropped and the sum is doubled per reflecting face.
+// Mirror corners are dropped through halo voxels whose stress is held at
+// zero (axes periodic for no component) or, on axes periodic for another
+// component, explicitly (z faces in the column partials, x and y faces at
+// the node); periodic components read the halo voxel (the periodic image)
+// as in the interior.
+//
+// The divergence at node J sums, over the 8 voxels J - 1 + b (b in {0,1}^3)
+// and the directions l, (2 b_l - 1) sigma_lq of the voxel's integration
+// point that owns the corner (HEX1: the single point; TETRA2: T1 when
+// b0 + b1 + b2 is odd, T2 when even).  The two z layers are summed first,
+// per voxel column: column (x, y) holds for each offset (b0, b1) and each q
+// the partial over b2 and l, from its own stresses of layers J2 - 1 and J2
+// (kept in registers), with the mirror corners of the z faces dropped; the
+// node then adds the partials of its four columns, dropping those of mirror
+// corners on the x and y faces.  sp / sc: stresses of the column's voxel in
+// layers J2 - 1 and J2, [point][Voigt] (HEX1: the point in both slots).
 template <typename R>
-__device__ __forceinline__ void node_div(const SolveDev& s, const FM_GLOBAL Ctrl* C, const R* __restrict__ sl, int cur,
-                                         int lx, int ly, const int J[3], R& accD) {
-  constexpr int PL_ = 12 * SD_VT;            // reals per voxel layer in the ring
-  const R* lay[2] = {sl + (cur ^ 1) * PL_, sl + cur * PL_};   // voxel layer J2 - 1, J2
-  const int64_t node = ((int64_t)J[2] * s.N[1] + J[1]) * s.N[0] + J[0];
-  FM_GLOBAL R* Dout = gmut((R*)s.Dring) + (int64_t)(C->m % s.depth) * 3 * s.Nn;
-  R D[3] = {0, 0, 0};
-  const int dm = s.mixed_wrap ? drop_bits(s, J) : 0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
-    const int r = (s.scheme == 1) ? (((b0 + b1 + b2) & 1) ? 0 : 1) : 0;   // odd corners T1, even T2
-    const R* p = lay[b2] + 6 * r * SD_VT + (ly + b1) * 32 + (lx + b0);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      R t = 0;
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        const R val = p[vidx(l, q) * SD_VT];
-        const int bl = l == 0 ? b0 : (l == 1 ? b1 : b2);
-        t += bl ? val : -val;
-      }
-      const int cm = (1 << (q * 6 + b0)) | (1 << (q * 6 + 2 + b1)) | (1 << (q * 6 + 4 + b2));
-      D[q] += (dm & cm) ? (R)0 : t;
-    }
-  }
-  const R f = (R)(0.25 / s.h);
+__device__ __forceinline__ void column_partials(const SolveDev& s, const R (&sp)[2][6], const R (&sc)[2][6], int J2,
+                                                R* __restrict__ P) {
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    bool kept = true;
-    R fq = f;
+    // mirror corners below / above a z face where u_q is not periodic along z
+    const bool zf = s.wrap[2] && s.kinds[q][2] != K_DFT;
+    const bool drop0 = zf && J2 == 0, drop1 = zf && J2 == s.n[2];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll
+      for (int b0 = 0; b0 < 2; ++b0) {
+        const int r0 = ((b0 + b1) & 1) ? 0 : 1;      // point of the b2 = 0 corner
+        const int r1 = r0 ^ 1;                       // and of the b2 = 1 corner
+        const R x0 = sp[r0][vidx(0, q)], y0 = sp[r0][vidx(1, q)], z0 = sp[r0][vidx(2, q)];
+        const R x1 = sc[r1][vidx(0, q)], y1 = sc[r1][vidx(1, q)], z1 = sc[r1][vidx(2, q)];
+        const R t0 = (b0 ? x0 : -x0) + (b1 ? y0 : -y0) - z0;
+        const R t1 = (b0 ? x1 : -x1) + (b1 ? y1 : -y1) + z1;
+        P[(q * 4 + b1 * 2 + b0) * SD_VT] = (drop0 ? (R)0 : t0) + (drop1 ? (R)0 : t1);
+      }
+  }
+}
+
+// Per-node constants of the x-y position: the factor of each component
+// (1/(4h), doubled per reflecting x or y face, 0 where the node is not kept
+// along x or y) and the mirror-corner drops of those faces, bit
+// (q * 4 + b1 * 2 + b0) set when column offset (b0, b1) is a mirror corner
+// of an axis periodic for another component.
+template <typename R>
+struct NodeXY {
+  R fq[3];
+  int drop;
+};
+
+template <typename R>
+__device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, int J0, int J1) {
+  NodeXY<R> r;
+  r.drop = 0;
+  const int J[2] = {J0, J1};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    R fq = (R)(0.25 / s.h);
+    bool kept = true;
+    int side[2] = {0, 0};                 // bit b: mirror side b dropped
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
       kept = kept && node_kept(s.kinds[q][i], s.n[i], J[i]);
-      if (s.kinds[q][i] != K_DFT && (J[i] == 0 || J[i] == s.n[i])) fq *= (R)2;
+      const bool face = s.kinds[q][i] != K_DFT && (J[i] == 0 || J[i] == s.n[i]);
+      if (face) fq *= (R)2;
+      if (face && s.wrap[i]) side[i] = J[i] == 0 ? 1 : 2;
     }
-    const R Dq = kept ? D[q] * fq : (R)0;
+    r.fq[q] = kept ? fq : (R)0;
+#pragma unroll
+    for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll
+      for (int b0 = 0; b0 < 2; ++b0)
+        if (((side[0] >> b0) & 1) || ((side[1] >> b1) & 1)) r.drop |= 1 << (q * 4 + b1 * 2 + b0);
+  }
+  return r;
+}
+
+// Divergence at the node of layer J2 (z factor fz per component: doubling on
+// a reflecting z face, 0 where not kept along z) from the column partials of
+// its four voxel columns; D written through Dn (this node in component 0).
+template <typename R>
+__device__ __forceinline__ void node_div(const R* __restrict__ P, int lx, int ly, const NodeXY<R>& nxy,
+                                         const R (&fz)[3], FM_GLOBAL R* Dn, int64_t Nn, R& accD) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    R D = 0;
+#pragma unroll
+    for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll
+      for (int b0 = 0; b0 < 2; ++b0) {
+        const R t = P[(q * 4 + b1 * 2 + b0) * SD_VT + (ly + b1) * 32 + (lx + b0)];
+        D += ((nxy.drop >> (q * 4 + b1 * 2 + b0)) & 1) ? (R)0 : t;
+      }
+    const R Dq = D * (nxy.fq[q] * fz[q]);
     accD += Dq * Dq;
-    Dout[q * s.Nn + node] = Dq;
+    Dn[q * Nn] = Dq;
   }
 }
 
 // Bytes of dynamic LDS of k_sdiv.
-__host__ __device__ inline size_t sdiv_lds_bytes(int rbytes) { return (size_t)2 * 12 * SD_VT * rbytes; }
+__host__ __device__ inline size_t sdiv_lds_bytes(int rbytes) { return (size_t)12 * SD_VT * rbytes; }
 
 template <typename R, int PL>
 __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
@@ -321,7 +357,7 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
   const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
   if (C->status != ST_RUNNING) return;
   extern __shared__ __align__(16) char smem[];
-  R* sl = (R*)smem;                                    // [2 layers][12][SD_VT]
+  R* sl = (R*)smem;                                    // column partials [12][SD_VT]
   const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
   const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * s.sd_zc;
   const int Z1 = min(Z0 + s.sd_zc, s.N[2]);
@@ -356,9 +392,18 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
     ustar_grad_column<R>(s, C, vx, vy, gA, gB);
     tet_cross_terms<R>(s, C, hc);
   }
+  // stresses of this column's voxel in the previous and current layer
+  // ([point][Voigt], zero on halo voxels; HEX1 duplicates its point)
+  R sprev[2][6], scur[2][6];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k] = 0;
+  const NodeXY<R> nxy = node_xy<R>(s, J0, J1);
+  const int64_t N01 = (int64_t)s.N[0] * s.N[1];
+  FM_GLOBAL R* Dcol = gmut((R*)s.Dring) + (int64_t)(C->m % s.depth) * 3 * s.Nn + (int64_t)J1 * s.N[0] + J0;
   int mt_cur = mat[((int64_t)map_vox(Z0 - 1, n2, s.wrap[2]) * n1 + vy) * n0 + vx];
   for (int zl = Z0 - 1; zl < Z1; ++zl) {
-    const int slot = (zl + 2) & 1;
     // material of the next voxel layer, fetched one layer ahead
     // (unconditional: the last layer reads a valid voxel it does not use, so the
     // load needs no branch and its wait can sink to the end of the layer)
@@ -381,7 +426,6 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
       const int64_t v = ((int64_t)vz * n1 + vy) * n0 + vx;
       const bool own = own_xy && zl >= Z0 && zl < n2;
       const bool zero_halo = zero_xy || (!s.wrap[2] && (zl < 0 || zl >= n2));
-      R* out = sl + slot * 12 * SD_VT + threadIdx.x;
       for (int r = 0; r < s.nppv; ++r) {
         R st[7], stn[7], sig[6];
         if (PL && s.has_state) {
@@ -396,7 +440,11 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
         else law_elastic<R>(law, P, eps[r], sig, st, stn);
         // halo voxels across faces of axes periodic for no component hold zero
 #pragma unroll
-        for (int k = 0; k < 6; ++k) out[(6 * r + k) * SD_VT] = zero_halo ? (R)0 : sig[k];
+        for (int k = 0; k < 6; ++k) {
+          const R val = zero_halo ? (R)0 : sig[k];
+          scur[0][k] = r == 0 ? val : scur[0][k];
+          scur[1][k] = r == 0 ? val : (r == 1 ? val : scur[1][k]);
+        }
         if (own) {
           R n2s = 0;
 #pragma unroll
@@ -408,13 +456,23 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
         }
       }
     }
-    __syncthreads();
-    if (zl >= Z0 && has_node) {
-      const int J[3] = {J0, J1, zl};
-      node_div<R>(s, C, sl, slot, lx, ly, J, acc[7]);
+    if (zl >= Z0) {
+      column_partials<R>(s, sprev, scur, zl, sl + threadIdx.x);
+      R fz[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const bool face = s.kinds[q][2] != K_DFT && (zl == 0 || zl == n2);
+        fz[q] = node_kept(s.kinds[q][2], n2, zl) ? (face ? (R)2 : (R)1) : (R)0;
+      }
+      __syncthreads();
+      if (has_node) node_div<R>(sl, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7]);
+      __syncthreads();
     }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k];
     mt_cur = mt_next;
-    __syncthreads();
   }
   __shared__ double outp[8];
   double accd[8];
