@@ -17,6 +17,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -763,6 +764,67 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   return 0;
 }
 
+// Persistent pipelined form of the strided E = 8 passes (FP32): at most
+// P_BLOCKS_PER_CU blocks per compute unit, a multiple of 8 blocks in all.
+constexpr int P_BLOCKS_PER_CU = 4;
+bool g_use_pipe = true;
+int g_num_cu = 0;
+
+// Resident blocks per compute unit of a kernel at a given dynamic LDS size
+// (cached: the launch path is also captured into graphs).
+inline int resident_blocks(const void* f, size_t lds) {
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({f, lds});
+  if (it != cache.end()) return it->second;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, WAVE_THREADS, lds) != hipSuccess) nb = 1;
+  nb = std::max(1, std::min(nb, P_BLOCKS_PER_CU));
+  cache[{f, lds}] = nb;
+  return nb;
+}
+
+template <int MODE, int KIND>
+void launch_w8p(int packed, int nwork, size_t lds, hipStream_t st, const PassDesc* P, const int2* wl,
+                const SolveDev* S) {
+  lds += p_extra_lds(MODE, KIND, packed);
+  const void* f = packed ? (const void*)k_wave_p<MODE, KIND, 1> : (const void*)k_wave_p<MODE, KIND, 0>;
+  int G = std::min(nwork, resident_blocks(f, lds) * g_num_cu);
+  if (G >= 8) G -= G % 8;
+  if (packed) hipLaunchKernelGGL((k_wave_p<MODE, KIND, 1>), dim3(G), dim3(WAVE_THREADS), lds, st, P, wl, nwork, S);
+  else hipLaunchKernelGGL((k_wave_p<MODE, KIND, 0>), dim3(G), dim3(WAVE_THREADS), lds, st, P, wl, nwork, S);
+}
+
+template <int MODE>
+void launch_w8p_kind(int kind, int packed, int nwork, size_t lds, hipStream_t st, const PassDesc* P,
+                     const int2* wl, const SolveDev* S) {
+  switch (kind) {
+    case K_DFT: launch_w8p<MODE, K_DFT>(packed, nwork, lds, st, P, wl, S); break;
+    case K_DCT1: launch_w8p<MODE, K_DCT1>(packed, nwork, lds, st, P, wl, S); break;
+    case K_DST1: launch_w8p<MODE, K_DST1>(packed, nwork, lds, st, P, wl, S); break;
+    case K_DCT3: launch_w8p<MODE, K_DCT3>(packed, nwork, lds, st, P, wl, S); break;
+    default: launch_w8p<MODE, K_DST3>(packed, nwork, lds, st, P, wl, S); break;
+  }
+}
+
+template <int MODE, int KIND>
+hipError_t set_w8p_lds(int big) {
+  hipError_t r = hipFuncSetAttribute((const void*)k_wave_p<MODE, KIND, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (r) return r;
+  return hipFuncSetAttribute((const void*)k_wave_p<MODE, KIND, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+}
+
+template <int MODE>
+hipError_t set_w8p_lds_kinds(int big) {
+  hipError_t r;
+  if ((r = set_w8p_lds<MODE, K_DFT>(big))) return r;
+  if ((r = set_w8p_lds<MODE, K_DCT1>(big))) return r;
+  if ((r = set_w8p_lds<MODE, K_DST1>(big))) return r;
+  if ((r = set_w8p_lds<MODE, K_DCT3>(big))) return r;
+  return set_w8p_lds<MODE, K_DST3>(big);
+}
+
 template <typename R, int MODE, int XP, int KIND>
 hipError_t set_w8_lds(int big) {
   hipError_t r = hipFuncSetAttribute((const void*)k_wave<R, MODE, XP, 8, KIND, 1>,
@@ -819,6 +881,14 @@ int set_lds_limits() {
   HIPCHK((set_wave_lds<R, 5>(big)));
   HIPCHK((set_wave_lds<R, 6>(big)));
   HIPCHK((set_wave_lds<R, 8>(big)));
+  if constexpr (sizeof(R) == 4) {
+    HIPCHK(set_w8p_lds_kinds<0>(big));
+    HIPCHK(set_w8p_lds_kinds<1>(big));
+    HIPCHK(set_w8p_lds_kinds<2>(big));
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  }
   HIPCHK((set_wave_lds<R, 12>(big)));
   HIPCHK((set_wave_lds<R, 16>(big)));
   HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -841,6 +911,12 @@ void launch_w8(int packed, dim3 grid, size_t lds, hipStream_t st, const PassDesc
 template <typename R, int MODE, int XP>
 void launch_w8_kind(int kind, int packed, dim3 grid, size_t lds, hipStream_t st, const PassDesc* P,
                     const int2* wl, const SolveDev* S) {
+  if constexpr (!XP && sizeof(R) == 4) {
+    if (g_use_pipe && g_num_cu > 0) {
+      launch_w8p_kind<MODE>(kind, packed, (int)grid.x, lds, st, P, wl, S);
+      return;
+    }
+  }
   switch (kind) {
     case K_DFT: launch_w8<R, MODE, XP, K_DFT>(packed, grid, lds, st, P, wl, S); break;
     case K_DCT1: launch_w8<R, MODE, XP, K_DCT1>(packed, grid, lds, st, P, wl, S); break;

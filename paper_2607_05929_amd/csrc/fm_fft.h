@@ -53,6 +53,15 @@ __device__ __forceinline__ void gstc(FM_GLOBAL char* base, uint32_t off, cx<R> c
   gst<R2>(base, off, v);
 }
 
+// LDS views (address space 3): ds instructions, counted by the LDS counter
+// only, so that waits on them do not wait for global loads in flight.
+#define FM_LDS __attribute__((address_space(3)))
+template <typename R> __device__ __forceinline__ cx<R> twid(const FM_LDS cx<R>* W, int t, bool inv) {
+  typedef R R2 __attribute__((ext_vector_type(2)));
+  const R2 v = *(const FM_LDS R2*)(W + t);
+  return inv ? mk<R>(v.x, -v.y) : mk<R>(v.x, v.y);
+}
+
 template <typename R> __device__ __forceinline__ cx<R> twid(const FM_GLOBAL cx<R>* W, int t, bool inv) {
   const cx<R> w = gldc<R>((const FM_GLOBAL char*)W, (uint32_t)t * (uint32_t)sizeof(cx<R>));
   return inv ? conj(w) : w;

@@ -17,6 +17,7 @@
 // array to coalesced stores.  No block barrier separates FFT stages; the
 // staging array is the only LDS.
 #pragma once
+#include <type_traits>
 #include "fm_pass.h"
 
 namespace fm {
@@ -204,8 +205,8 @@ __device__ __forceinline__ void wave_xpose(R* sb, cx<R> (&v)[8], WI widx, RI rid
   }
 }
 
-template <typename R>
-__device__ __forceinline__ void wave_fft8(cx<R> (&v)[8], const FM_GLOBAL cx<R>* W, R* sb, bool inv) {
+template <typename R, typename WP>
+__device__ __forceinline__ void wave_fft8(cx<R> (&v)[8], WP W, R* sb, bool inv) {
   const int t = threadIdx.x & 63;
   const int lo = t & 7, hi = t >> 3;
   auto t1_w = [&](int r) { return WT_PITCH * r + t; };                  // lane a + 8 b, register k1
@@ -275,6 +276,164 @@ __device__ __forceinline__ cx<R> mirror_val(const cx<R> (&v)[E], int r, int lane
 template <int XP>
 __device__ __forceinline__ int sidx(int c, int e, int pitch) {
   return XP ? c * pitch + e : e * pitch + c;
+}
+
+// Phases B and C of a pass: the block's staged tile (LDS, after a barrier)
+// -> pencil registers, transform(s) (and the Green operator in the fused z
+// pass), -> output staging.  Returns the output rows per column; the caller
+// places the barrier before the output staging is read.
+template <typename R, int MODE, int XP, int E, typename WP, typename GZ>
+__device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, bool packed, bool half, int cols,
+                                           int w, int t, int mlane0, const Tile& tl, int j0, int pitch, R* sr,
+                                           cx<R>* sc, R* wscr, WP W, const LaneTw<R>& ltw, const GreenCol<R>* gcol,
+                                           GZ gz) {
+  constexpr int L = 64 * E;
+  // ---------------- phase B: pencil -> registers, FFT ----------------
+  cx<R> v[E];
+  const int ca = packed ? 2 * w : w, cb = 2 * w + 1;   // columns of this pencil
+  if (MODE == 0 || MODE == 2) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int x = t + 64 * j;
+      int jn, sg;
+      ext_src(kind, n, x, jn, sg);
+      cx<R> z = mk<R>(0, 0);
+      if (sg) {
+        const int e = jn - j0;
+        if (packed) z = mk<R>(sr[sidx<XP>(ca, e, pitch)], sr[sidx<XP>(cb, e, pitch)]);
+        else z = sc[sidx<XP>(ca, e, pitch)];
+        if (sg < 0) z = scl(z, (R)-1);
+      }
+      v[j] = z;
+    }
+    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, false);
+    else wave_fft<R, E>(v, gconst((const cx<R>*)d.tw), ltw, false);
+  } else {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int m = spec_pos<E>(t, j);   // inverse input layout: lane t, register j
+      cx<R> z = mk<R>(0, 0);
+      if (half) {
+        // two Hermitian half spectra A (column ca) and B (column cb): Z = A + i B
+        const int km = m <= n / 2 ? m : n - m;
+        cx<R> A = sc[sidx<XP>(ca, km, pitch)], Bv = sc[sidx<XP>(cb, km, pitch)];
+        if (m > n / 2) { A = conj(A); Bv = conj(Bv); }
+        z = mk<R>(A.re - Bv.im, A.im + Bv.re);
+      } else {
+        int k;
+        R fr, fi;
+        if (spec_src<R>(kind, n, m, k, fr, fi)) {
+          const cx<R> g = packed ? mk<R>(sr[sidx<XP>(ca, k, pitch)], sr[sidx<XP>(cb, k, pitch)])
+                                 : sc[sidx<XP>(ca, k, pitch)];
+          z = mul(g, mk<R>(fr, fi));
+        }
+      }
+      v[j] = z;
+    }
+    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, true);
+    else wave_fft<R, E>(v, gconst((const cx<R>*)d.tw), ltw, true);
+  }
+
+  if (MODE == 2) {
+    // Green operator on the spectrum held in registers (lane t, register k1:
+    // position m = spec_pos(t, k1)); same structure-preserving scaling as the
+    // generic pass.
+    const bool okA = ca < tl.ncol, okB = packed ? cb < tl.ncol : false;
+    if (half) {
+      cx<R> nv[E];
+#pragma unroll
+      for (int k1 = 0; k1 < E; ++k1) {
+        const int m = spec_pos<E>(t, k1);
+        const cx<R> a = v[k1], b = conj(mirror_val<R, E>(v, k1, mlane0));
+        const cx<R> A = scl(add(a, b), (R)0.5);
+        const cx<R> Bv = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
+        const int mk_ = m <= n / 2 ? m : n - m;
+        const cx<R> sc2 = gz(mk_);
+        const R s2 = sc2.re, c2 = sc2.im;
+        const R fa = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
+        const R fb = okB ? green_apply<R>(gcol[cb], s2, c2) : (R)0;
+        nv[k1] = mk<R>(fa * A.re - fb * Bv.im, fa * A.im + fb * Bv.re);
+      }
+#pragma unroll
+      for (int k1 = 0; k1 < E; ++k1) v[k1] = nv[k1];
+    } else {
+#pragma unroll
+      for (int k1 = 0; k1 < E; ++k1) {
+        const int m = spec_pos<E>(t, k1);
+        int k;
+        R fr, fi;
+        if (!spec_src<R>(kind, n, m, k, fr, fi)) { v[k1] = mk<R>(0, 0); continue; }
+        const cx<R> sc2 = gz(k);
+        const R s2 = sc2.re, c2 = sc2.im;
+        if (packed) {
+          const R fa = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
+          const R fb = okB ? green_apply<R>(gcol[cb], s2, c2) : (R)0;
+          v[k1] = (fi == (R)0) ? mk<R>(v[k1].re * fa, v[k1].im * fb) : mk<R>(v[k1].re * fb, v[k1].im * fa);
+        } else {
+          const R g = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
+          v[k1] = scl(v[k1], g);
+        }
+      }
+    }
+    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, true);
+    else wave_fft<R, E>(v, gconst((const cx<R>*)d.tw), ltw, true);
+  }
+
+  // ---------------- phase C: registers -> staging ----------------
+  __syncthreads();     // every wavefront has finished reading its inputs
+  int outcnt;
+  if (MODE == 0) {
+    const int M = half ? n / 2 + 1 : n_freq(kind, n);
+    outcnt = M;
+    const int opitch = XP ? M + 1 : cols + 1;
+#pragma unroll
+    for (int k1 = 0; k1 < E; ++k1) {
+      const int m = spec_pos<E>(t, k1);
+      // coefficient index carried by position m (inverse of the Table 1 map)
+      int k = -1;
+      R fr = 1, fi = 0;
+      switch (kind) {
+        case K_DFT: if (m < M) k = m; break;
+        case K_DCT1: if (m <= n) k = m; break;
+        case K_DST1: if (m >= 1 && m <= n - 1) { k = m - 1; fr = 0; fi = 1; } break;
+        case K_DCT3: if ((m & 1) && m < 2 * n) { k = (m - 1) >> 1; fr = (R)0.5; } break;
+        default: if ((m & 1) && m < 2 * n) { k = (m - 1) >> 1; fr = 0; fi = (R)0.5; } break;
+      }
+      cx<R> pm = mk<R>(0, 0);
+      if (half) pm = conj(mirror_val<R, E>(v, k1, mlane0));    // shuffles: all lanes take part
+      if (k < 0) continue;
+      if (half) {
+        const cx<R> a = v[k1];
+        sc[sidx<XP>(ca, k, opitch)] = scl(add(a, pm), (R)0.5);
+        sc[sidx<XP>(cb, k, opitch)] = mk<R>((R)0.5 * (a.im - pm.im), (R)-0.5 * (a.re - pm.re));
+      } else {
+        const cx<R> g = mul(v[k1], mk<R>(fr, fi));
+        if (packed) { sr[sidx<XP>(ca, k, opitch)] = g.re; sr[sidx<XP>(cb, k, opitch)] = g.im; }
+        else sc[sidx<XP>(ca, k, opitch)] = g;
+      }
+    }
+  } else {
+    outcnt = n + 1;
+    const int opitch = XP ? n + 2 : cols + 1;
+    const R invL = (R)1 / (R)L;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int x = t + 64 * j;
+      // node j_node = x for x <= n; the periodic node n copies position 0
+      if (x > n) continue;
+      const int node = x;
+      const int srcx = node_src(kind, n, node);
+      cx<R> z = srcx < 0 ? mk<R>(0, 0) : scl(v[j], invL);
+      if (kind == K_DFT && x == n) z = mk<R>(0, 0);    // filled below from position 0
+      if (packed) { sr[sidx<XP>(ca, node, opitch)] = z.re; sr[sidx<XP>(cb, node, opitch)] = z.im; }
+      else sc[sidx<XP>(ca, node, opitch)] = z;
+      if (kind == K_DFT && x == 0) {
+        if (packed) { sr[sidx<XP>(ca, n, opitch)] = z.re; sr[sidx<XP>(cb, n, opitch)] = z.im; }
+        else sc[sidx<XP>(ca, n, opitch)] = z;
+      }
+    }
+  }
+  return outcnt;
 }
 
 // KIND >= 0 fixes the transform kind and PK the packing (1: two real
@@ -458,151 +617,12 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   __syncthreads();
   if (!CTRL_FIRST && C->status != ST_RUNNING) return;
 
-  // ---------------- phase B: pencil -> registers, FFT ----------------
-  cx<R> v[E];
-  const int ca = packed ? 2 * w : w, cb = 2 * w + 1;   // columns of this pencil
-  if (MODE == 0 || MODE == 2) {
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int x = t + 64 * j;
-      int jn, sg;
-      ext_src(kind, n, x, jn, sg);
-      cx<R> z = mk<R>(0, 0);
-      if (sg) {
-        const int e = jn - j0;
-        if (packed) z = mk<R>(sr[sidx<XP>(ca, e, pitch)], sr[sidx<XP>(cb, e, pitch)]);
-        else z = sc[sidx<XP>(ca, e, pitch)];
-        if (sg < 0) z = scl(z, (R)-1);
-      }
-      v[j] = z;
-    }
-    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, false);
-    else wave_fft<R, E>(v, W, ltw, false);
-  } else {
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int m = spec_pos<E>(t, j);   // inverse input layout: lane t, register j
-      cx<R> z = mk<R>(0, 0);
-      if (half) {
-        // two Hermitian half spectra A (column ca) and B (column cb): Z = A + i B
-        const int km = m <= n / 2 ? m : n - m;
-        cx<R> A = sc[sidx<XP>(ca, km, pitch)], Bv = sc[sidx<XP>(cb, km, pitch)];
-        if (m > n / 2) { A = conj(A); Bv = conj(Bv); }
-        z = mk<R>(A.re - Bv.im, A.im + Bv.re);
-      } else {
-        int k;
-        R fr, fi;
-        if (spec_src<R>(kind, n, m, k, fr, fi)) {
-          const cx<R> g = packed ? mk<R>(sr[sidx<XP>(ca, k, pitch)], sr[sidx<XP>(cb, k, pitch)])
-                                 : sc[sidx<XP>(ca, k, pitch)];
-          z = mul(g, mk<R>(fr, fi));
-        }
-      }
-      v[j] = z;
-    }
-    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, true);
-    else wave_fft<R, E>(v, W, ltw, true);
-  }
-
-  if (MODE == 2) {
-    // Green operator on the spectrum held in registers (lane t, register k1:
-    // position m = spec_pos(t, k1)); same structure-preserving scaling as the
-    // generic pass.
-    const FM_GLOBAL char* zs2 = (const FM_GLOBAL char*)gconst(d.gs2[2]);
-    const FM_GLOBAL char* zc2 = (const FM_GLOBAL char*)gconst(d.gc2[2]);
-    const bool okA = ca < tl.ncol, okB = packed ? cb < tl.ncol : false;
-    if (half) {
-      cx<R> nv[E];
-#pragma unroll
-      for (int k1 = 0; k1 < E; ++k1) {
-        const int m = spec_pos<E>(t, k1);
-        const cx<R> a = v[k1], b = conj(mirror_val<R, E>(v, k1, mlane0));
-        const cx<R> A = scl(add(a, b), (R)0.5);
-        const cx<R> Bv = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
-        const int mk_ = m <= n / 2 ? m : n - m;
-        const R s2 = (R)gld<double>(zs2, 8u * mk_), c2 = (R)gld<double>(zc2, 8u * mk_);
-        const R fa = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
-        const R fb = okB ? green_apply<R>(gcol[cb], s2, c2) : (R)0;
-        nv[k1] = mk<R>(fa * A.re - fb * Bv.im, fa * A.im + fb * Bv.re);
-      }
-#pragma unroll
-      for (int k1 = 0; k1 < E; ++k1) v[k1] = nv[k1];
-    } else {
-#pragma unroll
-      for (int k1 = 0; k1 < E; ++k1) {
-        const int m = spec_pos<E>(t, k1);
-        int k;
-        R fr, fi;
-        if (!spec_src<R>(kind, n, m, k, fr, fi)) { v[k1] = mk<R>(0, 0); continue; }
-        const R s2 = (R)gld<double>(zs2, 8u * k), c2 = (R)gld<double>(zc2, 8u * k);
-        if (packed) {
-          const R fa = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
-          const R fb = okB ? green_apply<R>(gcol[cb], s2, c2) : (R)0;
-          v[k1] = (fi == (R)0) ? mk<R>(v[k1].re * fa, v[k1].im * fb) : mk<R>(v[k1].re * fb, v[k1].im * fa);
-        } else {
-          const R g = okA ? green_apply<R>(gcol[ca], s2, c2) : (R)0;
-          v[k1] = scl(v[k1], g);
-        }
-      }
-    }
-    if constexpr (E == 8) wave_fft8<R>(v, W, wscr, true);
-    else wave_fft<R, E>(v, W, ltw, true);
-  }
-
-  // ---------------- phase C: registers -> staging ----------------
-  __syncthreads();     // every wavefront has finished reading its inputs
-  int outcnt;
-  if (MODE == 0) {
-    const int M = half ? n / 2 + 1 : n_freq(kind, n);
-    outcnt = M;
-    const int opitch = XP ? M + 1 : cols + 1;
-#pragma unroll
-    for (int k1 = 0; k1 < E; ++k1) {
-      const int m = spec_pos<E>(t, k1);
-      // coefficient index carried by position m (inverse of the Table 1 map)
-      int k = -1;
-      R fr = 1, fi = 0;
-      switch (kind) {
-        case K_DFT: if (m < M) k = m; break;
-        case K_DCT1: if (m <= n) k = m; break;
-        case K_DST1: if (m >= 1 && m <= n - 1) { k = m - 1; fr = 0; fi = 1; } break;
-        case K_DCT3: if ((m & 1) && m < 2 * n) { k = (m - 1) >> 1; fr = (R)0.5; } break;
-        default: if ((m & 1) && m < 2 * n) { k = (m - 1) >> 1; fr = 0; fi = (R)0.5; } break;
-      }
-      cx<R> pm = mk<R>(0, 0);
-      if (half) pm = conj(mirror_val<R, E>(v, k1, mlane0));    // shuffles: all lanes take part
-      if (k < 0) continue;
-      if (half) {
-        const cx<R> a = v[k1];
-        sc[sidx<XP>(ca, k, opitch)] = scl(add(a, pm), (R)0.5);
-        sc[sidx<XP>(cb, k, opitch)] = mk<R>((R)0.5 * (a.im - pm.im), (R)-0.5 * (a.re - pm.re));
-      } else {
-        const cx<R> g = mul(v[k1], mk<R>(fr, fi));
-        if (packed) { sr[sidx<XP>(ca, k, opitch)] = g.re; sr[sidx<XP>(cb, k, opitch)] = g.im; }
-        else sc[sidx<XP>(ca, k, opitch)] = g;
-      }
-    }
-  } else {
-    outcnt = n + 1;
-    const int opitch = XP ? n + 2 : cols + 1;
-    const R invL = (R)1 / (R)L;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int x = t + 64 * j;
-      // node j_node = x for x <= n; the periodic node n copies position 0
-      if (x > n) continue;
-      const int node = x;
-      const int srcx = node_src(kind, n, node);
-      cx<R> z = srcx < 0 ? mk<R>(0, 0) : scl(v[j], invL);
-      if (kind == K_DFT && x == n) z = mk<R>(0, 0);    // filled below from position 0
-      if (packed) { sr[sidx<XP>(ca, node, opitch)] = z.re; sr[sidx<XP>(cb, node, opitch)] = z.im; }
-      else sc[sidx<XP>(ca, node, opitch)] = z;
-      if (kind == K_DFT && x == 0) {
-        if (packed) { sr[sidx<XP>(ca, n, opitch)] = z.re; sr[sidx<XP>(cb, n, opitch)] = z.im; }
-        else sc[sidx<XP>(ca, n, opitch)] = z;
-      }
-    }
-  }
+  // z Green tables: sin^2 and cos^2 of the half modified frequency
+  const FM_GLOBAL char* zs2 = (const FM_GLOBAL char*)gconst(d.gs2[2]);
+  const FM_GLOBAL char* zc2 = (const FM_GLOBAL char*)gconst(d.gc2[2]);
+  auto gz = [&](int k) { return mk<R>((R)gld<double>(zs2, 8u * k), (R)gld<double>(zc2, 8u * k)); };
+  const int outcnt = wave_pencil<R, MODE, XP, E>(d, kind, n, packed, half, cols, w, t, mlane0, tl, j0, pitch, sr, sc,
+                                                wscr, W, ltw, gcol, gz);
   __syncthreads();
 
   // ---------------- phase D: staging -> memory (coalesced) ----------------
@@ -708,6 +728,149 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
             if (eb + u * step < outcnt) gst<R>(gout, o + u * ostep, tv[u]);
         }
       }
+  }
+}
+
+// Persistent, software-pipelined form of the strided E = 8 passes (FP32,
+// kind and packing fixed).  Block b takes the work items b, b + G, b + 2G,
+// ... (G = gridDim.x, a multiple of 8 when there are at least 8 items, so
+// that all items of a block run on the XCD the one-item-per-block launch
+// would use), and the tile loads of its next item are in flight while the
+// current one is transformed.  The twiddles and the z Green table are read
+// from LDS inside the transform: the vector-memory counter completes in
+// order, so waiting there for a later global load would also wait for the
+// prefetch.  LDS: per-wave transpose scratch, twiddles (L), z Green table
+// (p_gtab entries), staging.
+__host__ __device__ constexpr int p_gtab(int mode, int kind, int packed, int n) {
+  return mode != 2 ? 0 : (kind == K_DFT ? (packed ? n / 2 + 1 : n) : (kind == K_DCT1 ? n + 1 : kind == K_DST1 ? n - 1 : n));
+}
+__host__ __device__ constexpr size_t p_extra_lds(int mode, int kind, int packed) {
+  return (size_t)(512 + p_gtab(mode, kind, packed, 512 / kind_sf(kind))) * 2 * sizeof(float);
+}
+
+template <int MODE, int KIND, int PK>
+__global__ void __launch_bounds__(WAVE_THREADS) k_wave_p(const PassDesc* __restrict__ descs,
+                                                         const int2* __restrict__ work, int nwork,
+                                                         const SolveDev* __restrict__ S) {
+  typedef float R;
+  extern __shared__ __align__(16) char smem[];
+  __shared__ GreenCol<R> gcol[2 * WAVE_PENCILS];
+  constexpr int E = 8, L = 512;
+  constexpr int n = L / kind_sf(KIND);
+  constexpr bool packed = PK == 1;
+  constexpr int lcols = packed ? 4 : 3, cols = 1 << lcols;
+  constexpr bool half = packed && KIND == K_DFT;
+  constexpr bool cin = MODE == 1 ? (!packed || KIND == K_DFT) : !packed;
+  constexpr bool cout_ = MODE == 0 ? (!packed || KIND == K_DFT) : !packed;
+  constexpr uint32_t esi = cin ? 2 * sizeof(R) : sizeof(R);
+  constexpr uint32_t eso = cout_ ? 2 * sizeof(R) : sizeof(R);
+  // loaded node range (forward and fused passes) or spectral count (inverse)
+  constexpr int j0 = (MODE != 1 && (KIND == K_DST1 || KIND == K_DST3)) ? 1 : 0;
+  constexpr int nf = KIND == K_DCT1 ? n + 1 : KIND == K_DST1 ? n - 1 : n;
+  constexpr int cnt = (MODE == 1 && half) ? n / 2 + 1 : nf;
+  constexpr int rows_per = 64 >> lcols, step = WAVE_PENCILS * rows_per;
+  constexpr int UI = (cnt + step - 1) / step;
+  constexpr int pitch = cols + 1;
+  constexpr int GT = p_gtab(MODE, KIND, PK, n);
+  static_assert(GT <= WAVE_THREADS, "one Green entry per thread");
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int mlane0 = brev6((64 - brev6(t)) & 63);
+  const int c = t & (cols - 1), e0 = w * rows_per + (t >> lcols);
+  R* wscr = (R*)smem + w * WT_SIZE;
+  char* base = smem + WAVE_PENCILS * WT_SIZE * sizeof(R);
+  const FM_LDS cx<R>* tw = (const FM_LDS cx<R>*)(cx<R>*)base;
+  cx<R>* gtab = (cx<R>*)base + L;
+  char* stage = (char*)(gtab + GT);
+  R* sr = (R*)stage;
+  cx<R>* sc = (cx<R>*)stage;
+  if ((int)blockIdx.x >= nwork) return;
+  {
+    // the L = 512 twiddle table is the same for every item
+    const FM_GLOBAL char* W = (const FM_GLOBAL char*)gconst((const cx<R>*)descs[work[blockIdx.x].x].tw);
+    for (int i = threadIdx.x; i < L; i += WAVE_THREADS) ((cx<R>*)base)[i] = gldc<R>(W, i * (uint32_t)sizeof(cx<R>));
+  }
+  typedef typename std::conditional<cin, cx<R>, R>::type LT;
+  LT pre[UI];
+  cx<R> preg = mk<R>(0, 0);
+  auto issue = [&](int item) {
+    const int2 wk = work[item];
+    const PassDesc& d = descs[wk.x];
+    const int p0b = (wk.y % d.tiles_p0) * cols, p1 = wk.y / d.tiles_p0;
+    const bool okc = c < d.n_p0 - p0b;
+    const FM_GLOBAL char* gin =
+        (const FM_GLOBAL char*)gconst((const char*)d.in) + ((int64_t)p1 * d.in_s1 + p0b) * (int64_t)esi;
+    const uint32_t ostep = (uint32_t)step * (uint32_t)d.in_sa * esi;
+    const uint32_t o = ((uint32_t)c + (uint32_t)(j0 + e0) * (uint32_t)d.in_sa) * esi;
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+      if constexpr (cin) {
+        pre[u] = mk<R>(0, 0);
+        if (okc && e0 + u * step < cnt) pre[u] = gldc<R>(gin, o + u * ostep);
+      } else {
+        pre[u] = 0;
+        if (okc && e0 + u * step < cnt) pre[u] = gld<R>(gin, o + u * ostep);
+      }
+    }
+    if (MODE == 2 && (int)threadIdx.x < GT)
+      preg = mk<R>((R)gld<double>((const FM_GLOBAL char*)gconst(d.gs2[2]), 8u * threadIdx.x),
+                   (R)gld<double>((const FM_GLOBAL char*)gconst(d.gc2[2]), 8u * threadIdx.x));
+  };
+  const LaneTw<R> ltw{};
+  int item = blockIdx.x;
+  issue(item);
+  for (; item < nwork; item += gridDim.x) {
+    const int2 wk = work[item];
+    const PassDesc& d = descs[wk.x];
+    Tile tl;
+    tl.p0b = (wk.y % d.tiles_p0) * cols;
+    tl.p1 = wk.y / d.tiles_p0;
+    tl.ncol = min(cols, d.n_p0 - tl.p0b);
+    // stage the prefetched tile (and the z Green table)
+#pragma unroll
+    for (int u = 0; u < UI; ++u)
+      if (e0 + u * step < cnt) {
+        if constexpr (cin) sc[sidx<0>(c, e0 + u * step, pitch)] = pre[u];
+        else sr[sidx<0>(c, e0 + u * step, pitch)] = pre[u];
+      }
+    if (MODE == 2) {
+      if ((int)threadIdx.x < GT) gtab[threadIdx.x] = preg;
+      if ((int)threadIdx.x < cols)
+        gcol[threadIdx.x] = green_col<R>(d, min(tl.p0b + (int)threadIdx.x, d.n_p0 - 1), tl.p1);
+    }
+    __syncthreads();
+    const bool run = gconst(S[d.solve].ctrl)->status == ST_RUNNING;
+    if (item + (int)gridDim.x < nwork) issue(item + gridDim.x);
+    if (run) {
+      auto gz = [&](int k) { return gtab[k]; };
+      const int outcnt = wave_pencil<R, MODE, 0, E>(d, KIND, n, packed, half, cols, w, t, mlane0, tl, j0, pitch,
+                                                    sr, sc, wscr, tw, ltw, gcol, gz);
+      __syncthreads();
+      FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) +
+                             ((int64_t)tl.p1 * d.out_s1 + tl.p0b) * (int64_t)eso;
+      constexpr int UO = ((MODE == 0 ? (half ? n / 2 + 1 : nf) : n + 1) + step - 1) / step;
+      const uint32_t ostep = (uint32_t)step * (uint32_t)d.out_sa * eso;
+      const uint32_t o = ((uint32_t)c + (uint32_t)e0 * (uint32_t)d.out_sa) * eso;
+      if (c < tl.ncol) {
+        if constexpr (cout_) {
+          cx<R> tv[UO];
+#pragma unroll
+          for (int u = 0; u < UO; ++u)
+            if (e0 + u * step < outcnt) tv[u] = sc[sidx<0>(c, e0 + u * step, pitch)];
+#pragma unroll
+          for (int u = 0; u < UO; ++u)
+            if (e0 + u * step < outcnt) gstc<R>(gout, o + u * ostep, tv[u]);
+        } else {
+          R tv[UO];
+#pragma unroll
+          for (int u = 0; u < UO; ++u)
+            if (e0 + u * step < outcnt) tv[u] = sr[sidx<0>(c, e0 + u * step, pitch)];
+#pragma unroll
+          for (int u = 0; u < UO; ++u)
+            if (e0 + u * step < outcnt) gst<R>(gout, o + u * ostep, tv[u]);
+        }
+      }
+    }
+    __syncthreads();    // staging free for the next item
   }
 }
 
