@@ -400,6 +400,10 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
 #pragma unroll
     for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k] = 0;
   const NodeXY<R> nxy = node_xy<R>(s, J0, J1);
+  // FP32 corner carry: top corner 4 (FP64) and corners 5-7 minus it, per component
+  double cu4[3] = {0, 0, 0};
+  R cdt[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  int vz_prev = -2;
   const int64_t N01 = (int64_t)s.N[0] * s.N[1];
   FM_GLOBAL R* Dcol = gmut((R*)s.Dring) + (int64_t)(C->m % s.depth) * 3 * s.Nn + (int64_t)J1 * s.N[0] + J0;
   int mt_cur = mat[((int64_t)map_vox(Z0 - 1, n2, s.wrap[2]) * n1 + vy) * n0 + vx];
@@ -415,7 +419,39 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
       R eps[2][6];
       {
         R u[3][8], gs[3][3];
-        voxel_corners<R>(s, vx, vy, vz, u);
+        if constexpr (sizeof(R) == 4) {
+          // FP32: FP64 differences to corner 0, with the bottom face taken
+          // from the previous layer's top face when the layers are adjacent
+          // (same nodes, same differences: bitwise the full computation)
+          const bool carry = zl >= Z0 && vz == vz_prev + 1;
+          const int64_t base = (int64_t)vz * N01 + (int64_t)vy * s.N[0] + vx;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const FM_GLOBAL double* uq = gconst(s.uf) + q * s.Nn + base;
+            double u0;
+            if (carry) {
+              u0 = cu4[q];
+#pragma unroll
+              for (int c = 1; c < 4; ++c) u[q][c] = cdt[q][c - 1];
+            } else {
+              u0 = uq[0];
+#pragma unroll
+              for (int c = 1; c < 4; ++c) u[q][c] = (R)(uq[(c & 1) + (c >> 1) * s.N[0]] - u0);
+            }
+            u[q][0] = 0;
+            double top[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) top[c] = uq[(c & 1) + (c >> 1) * s.N[0] + N01];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) u[q][4 + c] = (R)(top[c] - u0);
+            cu4[q] = top[0];
+#pragma unroll
+            for (int c = 1; c < 4; ++c) cdt[q][c - 1] = (R)(top[c] - top[0]);
+          }
+          vz_prev = vz;
+        } else {
+          voxel_corners<R>(s, vx, vy, vz, u);
+        }
         const R zc = (R)((vz + 0.5) * s.h);
 #pragma unroll
         for (int l = 0; l < 3; ++l)

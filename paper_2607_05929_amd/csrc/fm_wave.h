@@ -740,7 +740,8 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
 // from LDS inside the transform: the vector-memory counter completes in
 // order, so waiting there for a later global load would also wait for the
 // prefetch.  LDS: per-wave transpose scratch, twiddles (L), z Green table
-// (p_gtab entries), staging.
+// (p_gtab entries), staging.  The single-transform DTT passes are held to
+// 64 VGPRs (8 wavefronts per SIMD, four blocks per compute unit).
 __host__ __device__ constexpr int p_gtab(int mode, int kind, int packed, int n) {
   return mode != 2 ? 0 : (kind == K_DFT ? (packed ? n / 2 + 1 : n) : (kind == K_DCT1 ? n + 1 : kind == K_DST1 ? n - 1 : n));
 }
@@ -749,7 +750,7 @@ __host__ __device__ constexpr size_t p_extra_lds(int mode, int kind, int packed)
 }
 
 template <int MODE, int KIND, int PK>
-__global__ void __launch_bounds__(WAVE_THREADS) k_wave_p(const PassDesc* __restrict__ descs,
+__global__ void __launch_bounds__(WAVE_THREADS, (MODE == 2 || KIND == K_DFT) ? 1 : 8) k_wave_p(const PassDesc* __restrict__ descs,
                                                          const int2* __restrict__ work, int nwork,
                                                          const SolveDev* __restrict__ S) {
   typedef float R;
