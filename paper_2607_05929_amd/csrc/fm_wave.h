@@ -205,8 +205,29 @@ __device__ __forceinline__ void wave_xpose(R* sb, cx<R> (&v)[8], WI widx, RI rid
   }
 }
 
-template <typename R, typename WP>
-__device__ __forceinline__ void wave_fft8(cx<R> (&v)[8], WP W, R* sb, bool inv) {
+// Twiddles of the E = 8 transform: the first stage takes W_512^(t k1)
+// (k1 = 1..7), the second W_64^(lo c) = W_512^(8 lo c) (c = 1..7).  From the
+// global L-table, or from an LDS table laid out per stage so that the reads
+// of a wavefront are conflict-free: [k1 - 1][t] (448 entries), then
+// [c - 1][lo] (56 entries, read as broadcasts).
+constexpr int TW8_LDS = 7 * 64 + 7 * 8;
+template <typename R>
+struct TwGlobal {
+  const FM_GLOBAL cx<R>* W;
+  __device__ __forceinline__ cx<R> s1(int t, int k1, bool inv) const { return twid<R>(W, t * k1, inv); }
+  __device__ __forceinline__ cx<R> s2(int lo, int c, bool inv) const { return twid<R>(W, 8 * lo * c, inv); }
+};
+template <typename R>
+struct TwLds {
+  const FM_LDS cx<R>* T;
+  __device__ __forceinline__ cx<R> s1(int t, int k1, bool inv) const { return twid<R>(T, (k1 - 1) * 64 + t, inv); }
+  __device__ __forceinline__ cx<R> s2(int lo, int c, bool inv) const {
+    return twid<R>(T, 7 * 64 + (c - 1) * 8 + lo, inv);
+  }
+};
+
+template <typename R, typename TW>
+__device__ __forceinline__ void wave_fft8(cx<R> (&v)[8], const TW& W, R* sb, bool inv) {
   const int t = threadIdx.x & 63;
   const int lo = t & 7, hi = t >> 3;
   auto t1_w = [&](int r) { return WT_PITCH * r + t; };                  // lane a + 8 b, register k1
@@ -217,22 +238,22 @@ __device__ __forceinline__ void wave_fft8(cx<R> (&v)[8], WP W, R* sb, bool inv) 
   if (!inv) {
     bfly8(v, sgn);                                                      // j -> k1
 #pragma unroll
-    for (int k1 = 1; k1 < 8; ++k1) v[k1] = mul(v[k1], twid<R>(W, t * k1, false));
+    for (int k1 = 1; k1 < 8; ++k1) v[k1] = mul(v[k1], W.s1(t, k1, false));
     wave_xpose<R>(sb, v, t1_w, t1_r);
     bfly8(v, sgn);                                                      // b -> c
 #pragma unroll
-    for (int c = 1; c < 8; ++c) v[c] = mul(v[c], twid<R>(W, 8 * lo * c, false));
+    for (int c = 1; c < 8; ++c) v[c] = mul(v[c], W.s2(lo, c, false));
     wave_xpose<R>(sb, v, t2_w, t2_r);
     bfly8(v, sgn);                                                      // a -> d
   } else {
     bfly8(v, sgn);                                                      // d -> a
     wave_xpose<R>(sb, v, t2_r, t2_w);
 #pragma unroll
-    for (int c = 1; c < 8; ++c) v[c] = mul(v[c], twid<R>(W, 8 * lo * c, true));
+    for (int c = 1; c < 8; ++c) v[c] = mul(v[c], W.s2(lo, c, true));
     bfly8(v, sgn);                                                      // c -> b
     wave_xpose<R>(sb, v, t1_r, t1_w);
 #pragma unroll
-    for (int k1 = 1; k1 < 8; ++k1) v[k1] = mul(v[k1], twid<R>(W, t * k1, true));
+    for (int k1 = 1; k1 < 8; ++k1) v[k1] = mul(v[k1], W.s1(t, k1, true));
     bfly8(v, sgn);                                                      // k1 -> j
   }
 }
@@ -622,7 +643,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   const FM_GLOBAL char* zc2 = (const FM_GLOBAL char*)gconst(d.gc2[2]);
   auto gz = [&](int k) { return mk<R>((R)gld<double>(zs2, 8u * k), (R)gld<double>(zc2, 8u * k)); };
   const int outcnt = wave_pencil<R, MODE, XP, E>(d, kind, n, packed, half, cols, w, t, mlane0, tl, j0, pitch, sr, sc,
-                                                wscr, W, ltw, gcol, gz);
+                                                wscr, TwGlobal<R>{W}, ltw, gcol, gz);
   __syncthreads();
 
   // ---------------- phase D: staging -> memory (coalesced) ----------------
@@ -786,9 +807,12 @@ __global__ void __launch_bounds__(WAVE_THREADS, (MODE == 2 || KIND == K_DFT) ? 1
   cx<R>* sc = (cx<R>*)stage;
   if ((int)blockIdx.x >= nwork) return;
   {
-    // the L = 512 twiddle table is the same for every item
+    // twiddles of the two stages (the L = 512 table is the same for every item)
     const FM_GLOBAL char* W = (const FM_GLOBAL char*)gconst((const cx<R>*)descs[work[blockIdx.x].x].tw);
-    for (int i = threadIdx.x; i < L; i += WAVE_THREADS) ((cx<R>*)base)[i] = gldc<R>(W, i * (uint32_t)sizeof(cx<R>));
+    for (int i = threadIdx.x; i < TW8_LDS; i += WAVE_THREADS) {
+      const int idx = i < 448 ? (i & 63) * ((i >> 6) + 1) : 8 * ((i - 448) & 7) * (((i - 448) >> 3) + 1);
+      ((cx<R>*)base)[i] = gldc<R>(W, (uint32_t)idx * (uint32_t)sizeof(cx<R>));
+    }
   }
   typedef typename std::conditional<cin, cx<R>, R>::type LT;
   LT pre[UI];
@@ -844,7 +868,7 @@ __global__ void __launch_bounds__(WAVE_THREADS, (MODE == 2 || KIND == K_DFT) ? 1
     if (run) {
       auto gz = [&](int k) { return gtab[k]; };
       const int outcnt = wave_pencil<R, MODE, 0, E>(d, KIND, n, packed, half, cols, w, t, mlane0, tl, j0, pitch,
-                                                    sr, sc, wscr, tw, ltw, gcol, gz);
+                                                    sr, sc, wscr, TwLds<R>{tw}, ltw, gcol, gz);
       __syncthreads();
       FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) +
                              ((int64_t)tl.p1 * d.out_s1 + tl.p0b) * (int64_t)eso;
