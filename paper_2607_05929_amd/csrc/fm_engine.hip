@@ -190,10 +190,11 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   g.sd_nt[0] = (int)cdiv(g.N[0], SD_TX);
   g.sd_nt[1] = (int)cdiv(g.N[1], SD_TY);
   // Layers per tile: SD_ZC, halved while the grid gives fewer than 8 blocks
-  // per compute unit (32 for the plastic laws, whose per-layer cost is high):
-  // each tile recomputes one voxel layer below it, so fewer layers cost more
-  // law evaluations but fill the GPU on small grids.
-  const int64_t want = (d->with_state ? 32 : 8) * 256;
+  // per compute unit (1 for the plastic laws, whose kernel holds one or two
+  // blocks per compute unit and whose per-layer cost is high): each tile
+  // recomputes one voxel layer below it, so fewer layers cost more law
+  // evaluations but fill the GPU on small grids.
+  const int64_t want = (d->with_state ? 1 : 8) * 256;
   g.sd_zc = SD_ZC;
   while (g.sd_zc > 1 && (int64_t)g.sd_nt[0] * g.sd_nt[1] * cdiv(g.N[2], g.sd_zc) < want) g.sd_zc /= 2;
   g.sd_nt[2] = (int)cdiv(g.N[2], g.sd_zc);
@@ -314,48 +315,6 @@ void cubic_mandel(double C11, double C12, double C44, const double R[3][3], doub
     for (int b = 0; b < 6; ++b) out[a * 6 + b] = w[a] * w[b] * Cr[MI[a]][MJ[a]][MI[b]][MJ[b]];
 }
 
-bool invert6(const double* A, double* out) {
-  double M[6][12];
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 12; ++j) M[i][j] = j < 6 ? A[i * 6 + j] : (j - 6 == i);
-  for (int p = 0; p < 6; ++p) {
-    int piv = p;
-    for (int q = p + 1; q < 6; ++q) if (std::fabs(M[q][p]) > std::fabs(M[piv][p])) piv = q;
-    if (std::fabs(M[piv][p]) < 1e-300) return false;
-    for (int c = 0; c < 12; ++c) std::swap(M[p][c], M[piv][c]);
-    const double ip = 1.0 / M[p][p];
-    for (int c = 0; c < 12; ++c) M[p][c] *= ip;
-    for (int q = 0; q < 6; ++q)
-      if (q != p) {
-        const double f = M[q][p];
-        for (int c = 0; c < 12; ++c) M[q][c] -= f * M[p][c];
-      }
-  }
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) out[i * 6 + j] = M[i][j + 6];
-  return true;
-}
-
-// 12 FCC systems {111}<110>: unit plane normals and slip directions.
-void fcc_systems(double m[12][3], double nrm[12][3]) {
-  const int N4[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
-  int cnt = 0;
-  for (int p = 0; p < 4; ++p) {
-    for (int a = 0; a < 3; ++a)
-      for (int b = a + 1; b < 3; ++b)
-        for (int sb = 1; sb >= -1; sb -= 2) {
-          int dvec[3] = {0, 0, 0};
-          dvec[a] = 1; dvec[b] = sb;
-          if (dvec[0] * N4[p][0] + dvec[1] * N4[p][1] + dvec[2] * N4[p][2] != 0) continue;
-          for (int i = 0; i < 3; ++i) {
-            m[cnt][i] = dvec[i] / std::sqrt(2.0);
-            nrm[cnt][i] = N4[p][i] / std::sqrt(3.0);
-          }
-          ++cnt;
-        }
-  }
-}
-
 int material_entry(const fm_material& mt, double* e /* MT_STRIDE */) {
   std::fill(e, e + MT_STRIDE, 0.0);
   switch (mt.law) {
@@ -378,25 +337,20 @@ int material_entry(const fm_material& mt, double* e /* MT_STRIDE */) {
       e[0] = mt.p[0]; e[1] = mt.p[1]; e[2] = mt.p[2]; e[3] = mt.p[3];
       return LAW_J2;
     case FM_LAW_CP: {
+      // the law works in the crystal frame: rotation and the three-entry
+      // cubic Mandel stiffness and compliance
+      const double C11 = mt.p[0], C12 = mt.p[1], C44 = mt.p[2];
+      if (!(C11 > C12) || !(C11 + 2 * C12 > 0) || !(C44 > 0)) return fail(FM_E_INVALID_ARG, "singular crystal stiffness");
       double R[3][3];
       quat_rot(mt.quat, R);
-      cubic_mandel(mt.p[0], mt.p[1], mt.p[2], R, e);
-      if (!invert6(e, e + 36)) return fail(FM_E_INVALID_ARG, "singular crystal stiffness");
-      double m[12][3], nn[12][3];
-      fcc_systems(m, nn);
-      for (int s = 0; s < 12; ++s) {
-        double ms[3] = {0, 0, 0}, ns[3] = {0, 0, 0};
-        for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) { ms[i] += R[i][j] * m[s][j]; ns[i] += R[i][j] * nn[s][j]; }
-        for (int a = 0; a < 6; ++a) {
-          const int i = MI[a], j = MJ[a];
-          const double pij = 0.5 * (ms[i] * ns[j] + ms[j] * ns[i]);
-          e[72 + s * 6 + a] = (a < 3 ? 1.0 : std::sqrt(2.0)) * pij;
-        }
-      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) e[i * 3 + j] = R[i][j];
+      const double det = (C11 - C12) * (C11 + 2 * C12);
+      e[9] = C11; e[10] = C12; e[11] = 2 * C44;
+      e[12] = (C11 + C12) / det; e[13] = -C12 / det; e[14] = 1 / (2 * C44);
       if (!(mt.p[3] > 0) || !(mt.p[4] >= 1) || !(mt.p[5] > 0) || !(mt.p[6] > mt.p[5]) || !(mt.p[7] >= 0))
         return fail(FM_E_INVALID_ARG, "crystal plasticity parameters out of range");
-      e[144] = mt.p[3]; e[145] = mt.p[4]; e[146] = mt.p[5]; e[147] = mt.p[6]; e[148] = mt.p[7];
+      e[15] = mt.p[3]; e[16] = mt.p[4]; e[17] = mt.p[5]; e[18] = mt.p[6]; e[19] = mt.p[7];
       return LAW_CP;
     }
     default:

@@ -7,8 +7,9 @@
 //   ANISO : C_M (6x6 Mandel stiffness, rotated cubic), upper triangle packed
 //           row by row (21 reals)
 //   J2    : lambda, mu, sy0, H
-//   CP    : C_M (36) | S_M = C_M^-1 (36) | Schmid tensors P_M (12 x 6) |
-//           gdot0, n, tau0, taus, theta0
+//   CP    : rotation R (9, row-major, sample = R crystal) | crystal-frame
+//           cubic Mandel stiffness c11, c12, c44m = 2 C44 | compliance s11,
+//           s12, s44m = 1 / (2 C44) | gdot0, n, tau0, taus, theta0
 // Internal variables (7): plastic strain (Voigt, tensor shears) and the
 // cumulated plastic strain p (J2) or accumulated slip Gamma (CP).
 #pragma once
@@ -62,120 +63,212 @@ __device__ __forceinline__ void mat6sym(PT Cp, const R x[6], R y[6]) {
   }
 }
 
+// |r|^n: binary powering for integral exponents up to 64 (the usual rate
+// sensitivities), exp(n log |r|) otherwise.
 template <typename R>
 __device__ __forceinline__ R powabs(R r, R n) {
   const R a = r < 0 ? -r : r;
   if (a == (R)0) return (R)0;
+  if (n >= (R)0 && n <= (R)64 && n == floor(n)) {
+    int k = (int)n;
+    R base = a, acc = 1;
+    while (k) {
+      if (k & 1) acc *= base;
+      base *= base;
+      k >>= 1;
+    }
+    return acc;
+  }
   return exp(n * log(a));
 }
 
-// Backward-Euler FCC crystal viscoplasticity (Newton on sigma_M, dGamma with
-// backtracking, started from the elastic predictor scaled to |tau|/tau_c <= 2;
-// stops at the tolerance or when no backtracked step lowers the residual).
+// FCC {111}<110> slip systems in the crystal frame (unnormalised slip
+// direction m and plane normal n, |m| = sqrt 2, |n| = sqrt 3).
+constexpr int FCC_M[12][3] = {{1, -1, 0}, {1, 0, -1}, {0, 1, -1}, {1, 1, 0}, {1, 0, 1},  {0, 1, -1},
+                              {1, 1, 0},  {1, 0, -1}, {0, 1, 1},  {1, -1, 0}, {1, 0, 1}, {0, 1, 1}};
+constexpr int FCC_N[12][3] = {{1, 1, 1},  {1, 1, 1},  {1, 1, 1},  {-1, 1, 1}, {-1, 1, 1}, {-1, 1, 1},
+                              {1, -1, 1}, {1, -1, 1}, {1, -1, 1}, {1, 1, -1}, {1, 1, -1}, {1, 1, -1}};
+constexpr int MND_I[6] = {0, 1, 2, 1, 0, 0}, MND_J[6] = {0, 1, 2, 2, 2, 1};
+
+// Mandel component a of the Schmid tensor sym(m (x) n) / (|m| |n|) of
+// system s (both compile-time after unrolling: the values fold to literals).
+template <typename R>
+__device__ __forceinline__ R schmid_c(int s, int a) {
+  const int i = MND_I[a], j = MND_J[a];
+  const int v2 = FCC_M[s][i] * FCC_N[s][j] + FCC_M[s][j] * FCC_N[s][i];   // 2 sym(m n)_ij
+  const double f = 0.5 / (1.41421356237309504880 * 1.73205080756887729353);
+  return (R)(a < 3 ? v2 * f : v2 * f * 1.41421356237309504880);
+}
+
+// Rotation of a symmetric tensor in Mandel form: to the crystal frame
+// (R^T A R) or back to the sample frame (R A R^T).
+template <typename R>
+__device__ __forceinline__ void mandel_rotate(const R (&Rm)[3][3], const R a[6], R b[6], bool to_crystal) {
+  const R is2 = (R)0.70710678118654752440, s2 = (R)1.41421356237309504880;
+  const R A[3][3] = {{a[0], is2 * a[5], is2 * a[4]}, {is2 * a[5], a[1], is2 * a[3]}, {is2 * a[4], is2 * a[3], a[2]}};
+  R T[3][3], B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      R t = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t += A[i][k] * (to_crystal ? Rm[k][j] : Rm[j][k]);
+      T[i][j] = t;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      R t = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t += (to_crystal ? Rm[k][i] : Rm[i][k]) * T[k][j];
+      B[i][j] = t;
+    }
+  b[0] = B[0][0]; b[1] = B[1][1]; b[2] = B[2][2];
+  b[3] = s2 * B[1][2]; b[4] = s2 * B[0][2]; b[5] = s2 * B[0][1];
+}
+
+// Backward-Euler FCC crystal viscoplasticity, solved in the crystal frame
+// (the equations are invariant under the rotation; there the Schmid tensors
+// are constants and the cubic compliance has three entries): Newton on
+// sigma_M, dGamma with backtracking, started from the elastic predictor
+// scaled to |tau|/tau_c <= 2; stops at the tolerance or when no backtracked
+// step lowers the residual.
 template <typename R, typename PT>
 __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[6], R epm[6], R& Gout) {
-  const PT Cm = P;
-  const PT Sm = P + 36;
-  const PT Pm = P + 72;
-  const R g0 = P[144], nx = P[145], tau0 = P[146], taus = P[147], th0 = P[148];
+  R Rm[3][3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Rm[i / 3][i % 3] = P[i];
+  const R c11 = P[9], c12 = P[10], c44 = P[11], s11 = P[12], s12 = P[13], s44 = P[14];
+  const R g0 = P[15], nx = P[16], tau0 = P[17], taus = P[18], th0 = P[19];
   R ee[6];
+  {
+    R es[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) es[i] = em[i] - epn[i];
+    mandel_rotate<R>(Rm, es, ee, true);
+  }
   R escale = (R)1e-9;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) { ee[i] = em[i] - epn[i]; escale = fmax(escale, fabs(ee[i])); }
+  for (int i = 0; i < 6; ++i) escale = fmax(escale, fabs(ee[i]));
+  auto comp = [&](const R* x, R* y) {       // crystal-frame compliance
+    y[0] = s11 * x[0] + s12 * (x[1] + x[2]);
+    y[1] = s11 * x[1] + s12 * (x[0] + x[2]);
+    y[2] = s11 * x[2] + s12 * (x[0] + x[1]);
+    y[3] = s44 * x[3]; y[4] = s44 * x[4]; y[5] = s44 * x[5];
+  };
+  auto tau_of = [&](const R* sg, int s_) {
+    R t = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) t += sg[i] * schmid_c<R>(s_, i);
+    return t;
+  };
   R sig[6];
-  mat6(Cm, ee, sig);
+  sig[0] = c11 * ee[0] + c12 * (ee[1] + ee[2]);
+  sig[1] = c11 * ee[1] + c12 * (ee[0] + ee[2]);
+  sig[2] = c11 * ee[2] + c12 * (ee[0] + ee[1]);
+  sig[3] = c44 * ee[3]; sig[4] = c44 * ee[4]; sig[5] = c44 * ee[5];
   R dG = 0;
   {
     const R tc = tau0 + (taus - tau0) * (1 - exp(-th0 * Gn / (taus - tau0)));
     R rmax = 0;
-    for (int s = 0; s < 12; ++s) {
-      R t = 0;
 #pragma unroll
-      for (int i = 0; i < 6; ++i) t += sig[i] * Pm[s * 6 + i];
-      rmax = fmax(rmax, fabs(t) / tc);
-    }
+    for (int s_ = 0; s_ < 12; ++s_) rmax = fmax(rmax, fabs(tau_of(sig, s_)));
+    rmax /= tc;
     if (rmax > (R)2) {
       const R f = (R)2 / rmax;
 #pragma unroll
       for (int i = 0; i < 6; ++i) sig[i] *= f;
     }
   }
+  const R ihs = (R)1 / (taus - tau0), iesc = (R)1 / escale;
   auto resid = [&](const R* sg, R d, R* Rs, R& Rg, R* gd, R& tc) -> R {
-    tc = tau0 + (taus - tau0) * (1 - exp(-th0 * (Gn + d) / (taus - tau0)));
+    tc = tau0 + (taus - tau0) * (1 - exp(-th0 * (Gn + d) * ihs));
+    const R itc = (R)1 / tc;
     R eps_s[6];
-    mat6<R>(Sm, sg, eps_s);
+    comp(sg, eps_s);
 #pragma unroll
     for (int i = 0; i < 6; ++i) Rs[i] = eps_s[i] - ee[i];
     R sum = 0;
-    for (int s = 0; s < 12; ++s) {
-      R t = 0;
 #pragma unroll
-      for (int i = 0; i < 6; ++i) t += sg[i] * Pm[s * 6 + i];
-      const R r = t / tc;
+    for (int s_ = 0; s_ < 12; ++s_) {
+      const R r = tau_of(sg, s_) * itc;
       const R g = g0 * powabs(r, nx) * (r < 0 ? (R)-1 : (R)1);
-      gd[s] = g;
+      gd[s_] = g;
       sum += fabs(g);
 #pragma unroll
-      for (int i = 0; i < 6; ++i) Rs[i] += dt * g * Pm[s * 6 + i];
+      for (int i = 0; i < 6; ++i) Rs[i] += dt * g * schmid_c<R>(s_, i);
     }
     Rg = d - dt * sum;
     R nr = fabs(Rg);
 #pragma unroll
     for (int i = 0; i < 6; ++i) nr = fmax(nr, fabs(Rs[i]));
-    return nr / escale;
+    return nr * iesc;
   };
   R Rs[6], Rg, gd[12], tc;
   R nr = resid(sig, dG, Rs, Rg, gd, tc);
   for (int it = 0; it < 80 && nr >= LawTol<R>::cp; ++it) {
     R J[7][8];
-    const R hG = th0 * exp(-th0 * (Gn + dG) / (taus - tau0));
+    const R hG = th0 * exp(-th0 * (Gn + dG) * ihs);
+    const R itc = (R)1 / tc;
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 7; ++i)
 #pragma unroll
-      for (int j = 0; j < 6; ++j) J[i][j] = Sm[i * 6 + j];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) J[i][6] = 0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) J[6][j] = 0;
+      for (int j = 0; j < 8; ++j) J[i][j] = 0;
+    J[0][0] = s11; J[1][1] = s11; J[2][2] = s11;
+    J[0][1] = J[1][0] = J[0][2] = J[2][0] = J[1][2] = J[2][1] = s12;
+    J[3][3] = s44; J[4][4] = s44; J[5][5] = s44;
     J[6][6] = 1;
-    for (int s = 0; s < 12; ++s) {
-      R t = 0;
 #pragma unroll
-      for (int i = 0; i < 6; ++i) t += sig[i] * Pm[s * 6 + i];
-      const R r = t / tc;
-      const R a = nx * g0 * powabs(r, nx - 1) / tc;
+    for (int s_ = 0; s_ < 12; ++s_) {
+      const R r = tau_of(sig, s_) * itc;
+      const R a = nx * g0 * powabs(r, nx - 1) * itc;
       const R sg = r < 0 ? (R)-1 : (R)1;
+      const R ca = dt * a, cb = dt * nx * gd[s_] * itc * hG, cc = dt * sg * a;
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        const R pi = Pm[s * 6 + i];
+        const R pi = schmid_c<R>(s_, i);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) J[i][j] += dt * a * pi * Pm[s * 6 + j];
-        J[i][6] -= dt * nx * gd[s] / tc * hG * pi;
-        J[6][i] -= dt * sg * a * pi;
+        for (int j = 0; j < 6; ++j) J[i][j] += ca * pi * schmid_c<R>(s_, j);
+        J[i][6] -= cb * pi;
+        J[6][i] -= cc * pi;
       }
-      J[6][6] += dt * nx * fabs(gd[s]) / tc * hG;
+      J[6][6] += dt * nx * fabs(gd[s_]) * itc * hG;
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) J[i][7] = Rs[i];
     J[6][7] = Rg;
-    // Gaussian elimination with partial pivoting
+    // Gaussian elimination, partial pivoting by compare-and-swap of the
+    // rows below the pivot (all indices compile-time: J stays in registers)
+    R ipv[7];
+#pragma unroll
     for (int p = 0; p < 7; ++p) {
-      int piv = p;
-      R best = fabs(J[p][p]);
-      for (int q = p + 1; q < 7; ++q) if (fabs(J[q][p]) > best) { best = fabs(J[q][p]); piv = q; }
-      if (piv != p)
-        for (int c = 0; c < 8; ++c) { const R tmp = J[p][c]; J[p][c] = J[piv][c]; J[piv][c] = tmp; }
-      const R ip = (R)1 / J[p][p];
+#pragma unroll
       for (int q = p + 1; q < 7; ++q) {
-        const R f = J[q][p] * ip;
-        for (int c = p; c < 8; ++c) J[q][c] -= f * J[p][c];
+        const bool sw = fabs(J[q][p]) > fabs(J[p][p]);
+#pragma unroll
+        for (int c = p; c < 8; ++c) {
+          const R x = J[p][c], y = J[q][c];
+          J[p][c] = sw ? y : x;
+          J[q][c] = sw ? x : y;
+        }
+      }
+      ipv[p] = (R)1 / J[p][p];
+#pragma unroll
+      for (int q = p + 1; q < 7; ++q) {
+        const R f = J[q][p] * ipv[p];
+#pragma unroll
+        for (int c = p + 1; c < 8; ++c) J[q][c] -= f * J[p][c];
       }
     }
     R dx[7];
+#pragma unroll
     for (int p = 6; p >= 0; --p) {
       R t = J[p][7];
+#pragma unroll
       for (int c = p + 1; c < 7; ++c) t -= J[p][c] * dx[c];
-      dx[p] = t / J[p][p];
+      dx[p] = t * ipv[p];
     }
     R lam = 1;
     R s_new[6], d_new, Rs2[6], Rg2, gd2[12], tc2, nr2 = nr;
@@ -195,15 +288,23 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
 #pragma unroll
     for (int i = 0; i < 6; ++i) { sig[i] = s_new[i]; Rs[i] = Rs2[i]; }
     dG = d_new; Rg = Rg2; tc = tc2; nr = nr2;
-    for (int s = 0; s < 12; ++s) gd[s] = gd2[s];
+#pragma unroll
+    for (int s_ = 0; s_ < 12; ++s_) gd[s_] = gd2[s_];
   }
+  // back to the sample frame: stress and plastic strain increment
+  R dp[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    sm[i] = sig[i];
-    R e = epn[i];
-    for (int s = 0; s < 12; ++s) e += dt * gd[s] * Pm[s * 6 + i];
-    epm[i] = e;
+    R e = 0;
+#pragma unroll
+    for (int s_ = 0; s_ < 12; ++s_) e += dt * gd[s_] * schmid_c<R>(s_, i);
+    dp[i] = e;
   }
+  mandel_rotate<R>(Rm, sig, sm, false);
+  R dps[6];
+  mandel_rotate<R>(Rm, dp, dps, false);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) epm[i] = epn[i] + dps[i];
   Gout = Gn + dG;
 }
 
@@ -284,6 +385,31 @@ __device__ __forceinline__ void law_eval(int law, PT P, const R eps[6], R sig[6]
     from_mandel(sm, sig);
     from_mandel(epm, stn);
     stn[6] = G;
+  }
+}
+
+// Plastic laws evaluated in FP64 whatever the storage precision.  The flow
+// rule's power law (exponent n = 20 in the FCC workloads) amplifies the
+// rounding of a resolved shear n-fold, so an FP32 return mapping only
+// reaches ~1e-6 relative accuracy, the size of the equilibrium tolerance,
+// and its stress is not a smooth function of the strain at that level; in
+// FP64 it is, and the FP32 solve converges as the FP64 one does.
+template <typename R, typename PT>
+__device__ __forceinline__ void law_eval_f64(int law, PT P, const R eps[6], R sig[6], const R st[7], R stn[7],
+                                             double dt) {
+  if constexpr (sizeof(R) == 8) {
+    law_eval<double>(law, P, eps, sig, st, stn, dt);
+  } else {
+    double e[6], s[6], a[7], b[7];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) e[i] = eps[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) a[i] = st[i];
+    law_eval<double>(law, P, e, s, a, b, dt);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sig[i] = (R)s[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) stn[i] = (R)b[i];
   }
 }
 

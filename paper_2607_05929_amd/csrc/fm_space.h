@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(256) k_commit(const SolveDev* __restrict__ S, 
         for (int k = 0; k < 7; ++k) st[k] = 0;
       }
       R sig[6];
-      if (PL) law_eval<R>(law, P, eps[r], sig, st, stn, (R)C->dt);
+      if (PL) law_eval_f64<R>(law, P, eps[r], sig, st, stn, C->dt);
       else law_elastic<R>(law, P, eps[r], sig, st, stn);
       if (PL && s.has_state && (law == LAW_J2 || law == LAW_CP)) {
 #pragma unroll
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
 #pragma unroll
           for (int k = 0; k < 7; ++k) st[k] = 0;
         }
-        if (PL) law_eval<R>(law, P, eps[r], sig, st, stn, (R)C->dt);
+        if (PL) law_eval_f64<R>(law, P, eps[r], sig, st, stn, C->dt);
         else law_elastic<R>(law, P, eps[r], sig, st, stn);
         // halo voxels across faces of axes periodic for no component hold zero
 #pragma unroll
