@@ -763,6 +763,37 @@ void launch_w8p_kind(int kind, int packed, int nwork, size_t lds, hipStream_t st
 }
 
 template <int MODE, int KIND>
+void launch_w8px(int nwork, size_t lds, hipStream_t st, const PassDesc* P, const int2* wl, const SolveDev* S) {
+  lds += px_extra_lds();
+  const void* f = (const void*)k_wave_px<MODE, KIND>;
+  int G = std::min(nwork, resident_blocks(f, lds) * g_num_cu);
+  if (G >= 8) G -= G % 8;
+  hipLaunchKernelGGL((k_wave_px<MODE, KIND>), dim3(G), dim3(WAVE_THREADS), lds, st, P, wl, nwork, S);
+}
+
+template <int MODE>
+void launch_w8px_kind(int kind, int nwork, size_t lds, hipStream_t st, const PassDesc* P, const int2* wl,
+                      const SolveDev* S) {
+  switch (kind) {
+    case K_DFT: launch_w8px<MODE, K_DFT>(nwork, lds, st, P, wl, S); break;
+    case K_DCT1: launch_w8px<MODE, K_DCT1>(nwork, lds, st, P, wl, S); break;
+    case K_DST1: launch_w8px<MODE, K_DST1>(nwork, lds, st, P, wl, S); break;
+    case K_DCT3: launch_w8px<MODE, K_DCT3>(nwork, lds, st, P, wl, S); break;
+    default: launch_w8px<MODE, K_DST3>(nwork, lds, st, P, wl, S); break;
+  }
+}
+
+template <int MODE>
+hipError_t set_w8px_lds_kinds(int big) {
+  hipError_t r;
+  if ((r = hipFuncSetAttribute((const void*)k_wave_px<MODE, K_DFT>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+  if ((r = hipFuncSetAttribute((const void*)k_wave_px<MODE, K_DCT1>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+  if ((r = hipFuncSetAttribute((const void*)k_wave_px<MODE, K_DST1>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+  if ((r = hipFuncSetAttribute((const void*)k_wave_px<MODE, K_DCT3>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) return r;
+  return hipFuncSetAttribute((const void*)k_wave_px<MODE, K_DST3>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+}
+
+template <int MODE, int KIND>
 hipError_t set_w8p_lds(int big) {
   hipError_t r = hipFuncSetAttribute((const void*)k_wave_p<MODE, KIND, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (r) return r;
@@ -839,6 +870,7 @@ int set_lds_limits() {
     HIPCHK(set_w8p_lds_kinds<0>(big));
     HIPCHK(set_w8p_lds_kinds<1>(big));
     HIPCHK(set_w8p_lds_kinds<2>(big));
+    HIPCHK(set_w8px_lds_kinds<0>(big));
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -868,6 +900,14 @@ void launch_w8_kind(int kind, int packed, dim3 grid, size_t lds, hipStream_t st,
   if constexpr (!XP && sizeof(R) == 4) {
     if (g_use_pipe && g_num_cu > 0) {
       launch_w8p_kind<MODE>(kind, packed, (int)grid.x, lds, st, P, wl, S);
+      return;
+    }
+  } else if constexpr (XP && MODE == 0 && sizeof(R) == 4) {
+    // (the x inverse pass stays one tile per block: its u^f update reads
+    // global memory after the transform, and those waits would take in the
+    // prefetch; measured slower pipelined)
+    if (g_use_pipe && g_num_cu > 0 && packed) {
+      launch_w8px_kind<MODE>(kind, (int)grid.x, lds, st, P, wl, S);
       return;
     }
   }

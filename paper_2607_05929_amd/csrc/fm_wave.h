@@ -457,6 +457,86 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
   return outcnt;
 }
 
+// Phase D of the x passes: output staging -> memory.  Forward: the
+// coefficient rows; inverse: u^f += w - sum_k beta_k delta_k and the new
+// increment into the ring (FP64 accumulator).
+template <typename R, int MODE, int UD>
+__device__ __forceinline__ void wave_store_x(const PassDesc& d, const FM_GLOBAL Ctrl* C, const Tile& tl,
+                                             int64_t out_blk, int outcnt, bool cout_, uint32_t eso, const R* sr,
+                                             const cx<R>* sc, int w, int t) {
+  const int opitch = outcnt + 1;
+  const int s1 = (int)d.out_s1;
+  if (MODE == 0) {
+    FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) + out_blk * (int64_t)eso;
+    for (int c = w; c < tl.ncol; c += WAVE_PENCILS) {
+      const uint32_t rowe = (uint32_t)(c * s1);
+      for (int eb = t; eb < outcnt; eb += UD * 64) {
+        if (cout_) {
+          cx<R> tv[UD];
+#pragma unroll
+          for (int u = 0; u < UD; ++u)
+            if (eb + 64 * u < outcnt) tv[u] = sc[sidx<1>(c, eb + 64 * u, opitch)];
+#pragma unroll
+          for (int u = 0; u < UD; ++u)
+            if (eb + 64 * u < outcnt) gstc<R>(gout, (rowe + (uint32_t)(eb + 64 * u)) * eso, tv[u]);
+        } else {
+          R tv[UD];
+#pragma unroll
+          for (int u = 0; u < UD; ++u)
+            if (eb + 64 * u < outcnt) tv[u] = sr[sidx<1>(c, eb + 64 * u, opitch)];
+#pragma unroll
+          for (int u = 0; u < UD; ++u)
+            if (eb + 64 * u < outcnt) gst<R>(gout, (rowe + (uint32_t)(eb + 64 * u)) * eso, tv[u]);
+        }
+      }
+    }
+  } else {
+    // x inverse: u^f += w - sum_k beta_k delta_k, new increment into the ring
+    const int nb = C->n_b;
+    R be[MAX_DEPTH];
+    const FM_GLOBAL char* dsrc[MAX_DEPTH];
+    const FM_GLOBAL char* ring = (const FM_GLOBAL char*)gconst((const R*)d.ring);
+#pragma unroll
+    for (int q = 0; q < MAX_DEPTH; ++q) {
+      be[q] = q < nb ? (R)C->beta[q] : (R)0;
+      dsrc[q] = ring + ((int64_t)(q < nb ? C->slot_b[q] : 0) * d.ring_stride + out_blk) * (int64_t)sizeof(R);
+    }
+    FM_GLOBAL char* dw = (FM_GLOBAL char*)gmut((R*)d.ring) +
+                         ((int64_t)C->slot_w * d.ring_stride + out_blk) * (int64_t)sizeof(R);
+    FM_GLOBAL char* guf = (FM_GLOBAL char*)gmut(d.uf) + out_blk * (int64_t)sizeof(double);
+    constexpr int UX = 4;
+    for (int c = w; c < tl.ncol; c += WAVE_PENCILS) {
+      const uint32_t rowe = (uint32_t)(c * s1);
+      for (int eb = t; eb < outcnt; eb += UX * 64) {
+        R dl[UX];
+        double uo[UX];
+#pragma unroll
+        for (int u = 0; u < UX; ++u) {
+          const int e = eb + 64 * u;
+          if (e < outcnt) {
+            const uint32_t o = rowe + (uint32_t)e;
+            R a = sr[sidx<1>(c, e, opitch)];
+#pragma unroll
+            for (int q = 0; q < MAX_DEPTH; ++q)
+              if (q < nb) a -= be[q] * gld<R>(dsrc[q], o * (uint32_t)sizeof(R));
+            dl[u] = a;
+            uo[u] = gld<double>(guf, o * 8u);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UX; ++u) {
+          const int e = eb + 64 * u;
+          if (e < outcnt) {
+            const uint32_t o = rowe + (uint32_t)e;
+            gst<R>(dw, o * (uint32_t)sizeof(R), dl[u]);
+            gst<double>(guf, o * 8u, uo[u] + (double)dl[u]);
+          }
+        }
+      }
+    }
+  }
+}
+
 // KIND >= 0 fixes the transform kind and PK the packing (1: two real
 // columns per pencil, 0: one complex column) at compile time, and with them
 // the axis length (n = L / S_f), the tile width, the element types and every
@@ -649,77 +729,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   // ---------------- phase D: staging -> memory (coalesced) ----------------
   constexpr int UD = SK && !XP ? (CNT_OUT + STEP_C - 1) / STEP_C : 8;
   if (XP) {
-    const int opitch = outcnt + 1;
-    const int s1 = (int)d.out_s1;
-    if (MODE == 0) {
-      FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) + out_blk * (int64_t)eso;
-      for (int c = w; c < tl.ncol; c += WAVE_PENCILS) {
-        const uint32_t rowe = (uint32_t)(c * s1);
-        for (int eb = t; eb < outcnt; eb += UD * 64) {
-          if (cout_) {
-            cx<R> tv[UD];
-#pragma unroll
-            for (int u = 0; u < UD; ++u)
-              if (eb + 64 * u < outcnt) tv[u] = sc[sidx<1>(c, eb + 64 * u, opitch)];
-#pragma unroll
-            for (int u = 0; u < UD; ++u)
-              if (eb + 64 * u < outcnt) gstc<R>(gout, (rowe + (uint32_t)(eb + 64 * u)) * eso, tv[u]);
-          } else {
-            R tv[UD];
-#pragma unroll
-            for (int u = 0; u < UD; ++u)
-              if (eb + 64 * u < outcnt) tv[u] = sr[sidx<1>(c, eb + 64 * u, opitch)];
-#pragma unroll
-            for (int u = 0; u < UD; ++u)
-              if (eb + 64 * u < outcnt) gst<R>(gout, (rowe + (uint32_t)(eb + 64 * u)) * eso, tv[u]);
-          }
-        }
-      }
-    } else {
-      // x inverse: u^f += w - sum_k beta_k delta_k, new increment into the ring
-      const int nb = C->n_b;
-      R be[MAX_DEPTH];
-      const FM_GLOBAL char* dsrc[MAX_DEPTH];
-      const FM_GLOBAL char* ring = (const FM_GLOBAL char*)gconst((const R*)d.ring);
-#pragma unroll
-      for (int q = 0; q < MAX_DEPTH; ++q) {
-        be[q] = q < nb ? (R)C->beta[q] : (R)0;
-        dsrc[q] = ring + ((int64_t)(q < nb ? C->slot_b[q] : 0) * d.ring_stride + out_blk) * (int64_t)sizeof(R);
-      }
-      FM_GLOBAL char* dw = (FM_GLOBAL char*)gmut((R*)d.ring) +
-                           ((int64_t)C->slot_w * d.ring_stride + out_blk) * (int64_t)sizeof(R);
-      FM_GLOBAL char* guf = (FM_GLOBAL char*)gmut(d.uf) + out_blk * (int64_t)sizeof(double);
-      constexpr int UX = 4;
-      for (int c = w; c < tl.ncol; c += WAVE_PENCILS) {
-        const uint32_t rowe = (uint32_t)(c * s1);
-        for (int eb = t; eb < outcnt; eb += UX * 64) {
-          R dl[UX];
-          double uo[UX];
-#pragma unroll
-          for (int u = 0; u < UX; ++u) {
-            const int e = eb + 64 * u;
-            if (e < outcnt) {
-              const uint32_t o = rowe + (uint32_t)e;
-              R a = sr[sidx<1>(c, e, opitch)];
-#pragma unroll
-              for (int q = 0; q < MAX_DEPTH; ++q)
-                if (q < nb) a -= be[q] * gld<R>(dsrc[q], o * (uint32_t)sizeof(R));
-              dl[u] = a;
-              uo[u] = gld<double>(guf, o * 8u);
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < UX; ++u) {
-            const int e = eb + 64 * u;
-            if (e < outcnt) {
-              const uint32_t o = rowe + (uint32_t)e;
-              gst<R>(dw, o * (uint32_t)sizeof(R), dl[u]);
-              gst<double>(guf, o * 8u, uo[u] + (double)dl[u]);
-            }
-          }
-        }
-      }
-    }
+    wave_store_x<R, MODE, UD>(d, C, tl, out_blk, outcnt, cout_, eso, sr, sc, w, t);
   } else {
     FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) + out_blk * (int64_t)eso;
     const int opitch = cols + 1;
@@ -894,6 +904,143 @@ __global__ void __launch_bounds__(WAVE_THREADS, (MODE == 2 || KIND == K_DFT) ? 1
             if (e0 + u * step < outcnt) gst<R>(gout, o + u * ostep, tv[u]);
         }
       }
+    }
+    __syncthreads();    // staging free for the next item
+  }
+}
+
+// Persistent, software-pipelined form of the x forward pass of length 512
+// (FP32, two real rows per pencil): as k_wave_p, with the rows of the next
+// tile prefetched while the current one is transformed.  The prefetch takes
+// the first Anderson slot; the other slots of an Anderson iteration are read
+// when the tile is staged.  The template also covers the x inverse pass
+// (MODE 1), which the engine keeps on k_wave: measured slower pipelined.
+__host__ __device__ constexpr size_t px_extra_lds() { return (size_t)512 * 2 * sizeof(float); }
+
+template <int MODE, int KIND>
+__global__ void __launch_bounds__(WAVE_THREADS, (KIND == K_DFT || MODE == 1) ? 1 : 8) k_wave_px(const PassDesc* __restrict__ descs,
+                                                                              const int2* __restrict__ work, int nwork,
+                                                                              const SolveDev* __restrict__ S) {
+  typedef float R;
+  extern __shared__ __align__(16) char smem[];
+  constexpr int E = 8, L = 512;
+  constexpr int n = L / kind_sf(KIND);
+  constexpr bool packed = true, half = KIND == K_DFT;
+  constexpr int cols = 2 * WAVE_PENCILS;
+  constexpr bool cin = MODE == 1 && half;
+  constexpr bool cout_ = MODE == 0 && half;
+  constexpr uint32_t esi = cin ? 2 * sizeof(R) : sizeof(R);
+  constexpr uint32_t eso = cout_ ? 2 * sizeof(R) : sizeof(R);
+  constexpr int j0 = (MODE == 0 && (KIND == K_DST1 || KIND == K_DST3)) ? 1 : 0;
+  constexpr int nf = KIND == K_DCT1 ? n + 1 : KIND == K_DST1 ? n - 1 : n;
+  constexpr int cnt = (MODE == 1 && half) ? n / 2 + 1 : nf;
+  constexpr int U1 = (cnt + 63) / 64;
+  constexpr int pitch = cnt + 1;
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int mlane0 = brev6((64 - brev6(t)) & 63);
+  R* wscr = (R*)smem + w * WT_SIZE;
+  char* base = smem + WAVE_PENCILS * WT_SIZE * sizeof(R);
+  const FM_LDS cx<R>* tw = (const FM_LDS cx<R>*)(cx<R>*)base;
+  char* stage = (char*)((cx<R>*)base + L);
+  R* sr = (R*)stage;
+  cx<R>* sc = (cx<R>*)stage;
+  if ((int)blockIdx.x >= nwork) return;
+  {
+    const FM_GLOBAL char* W = (const FM_GLOBAL char*)gconst((const cx<R>*)descs[work[blockIdx.x].x].tw);
+    for (int i = threadIdx.x; i < TW8_LDS; i += WAVE_THREADS) {
+      const int idx = i < 448 ? (i & 63) * ((i >> 6) + 1) : 8 * ((i - 448) & 7) * (((i - 448) >> 3) + 1);
+      ((cx<R>*)base)[i] = gldc<R>(W, (uint32_t)idx * (uint32_t)sizeof(cx<R>));
+    }
+  }
+  typedef typename std::conditional<cin, cx<R>, R>::type LT;
+  LT pre[2][U1];
+  // rows of a tile's input: first Anderson slot (forward) or the spectrum (inverse)
+  auto row_base = [&](const PassDesc& d, int p0b) -> const FM_GLOBAL char* {
+    if (MODE == 0) {
+      const FM_GLOBAL Ctrl* C = gconst(S[d.solve].ctrl);
+      return (const FM_GLOBAL char*)gconst((const R*)d.ring) +
+             ((int64_t)C->slot_d[0] * d.ring_stride + (int64_t)p0b * d.in_s1) * (int64_t)sizeof(R);
+    }
+    return (const FM_GLOBAL char*)gconst((const char*)d.in) + (int64_t)p0b * d.in_s1 * (int64_t)esi;
+  };
+  auto issue = [&](int item) {
+    const int2 wk = work[item];
+    const PassDesc& d = descs[wk.x];
+    const int p0b = wk.y * cols;
+    const int ncol = d.n_p0 - p0b;
+    const FM_GLOBAL char* gin = row_base(d, p0b);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int c = w + WAVE_PENCILS * r;
+      const uint32_t rowe = (uint32_t)(c * (int)d.in_s1 + j0);
+#pragma unroll
+      for (int u = 0; u < U1; ++u) {
+        const int e = t + 64 * u;
+        if constexpr (cin) {
+          pre[r][u] = mk<R>(0, 0);
+          if (c < ncol && e < cnt) pre[r][u] = gldc<R>(gin, (rowe + (uint32_t)e) * esi);
+        } else {
+          pre[r][u] = 0;
+          if (c < ncol && e < cnt) pre[r][u] = gld<R>(gin, (rowe + (uint32_t)e) * esi);
+        }
+      }
+    }
+  };
+  const LaneTw<R> ltw{};
+  const GreenCol<R>* nogreen = nullptr;
+  auto nogz = [](int) { return mk<R>(0, 0); };
+  int item = blockIdx.x;
+  issue(item);
+  for (; item < nwork; item += gridDim.x) {
+    const int2 wk = work[item];
+    const PassDesc& d = descs[wk.x];
+    const FM_GLOBAL Ctrl* C = gconst(S[d.solve].ctrl);
+    Tile tl;
+    tl.p0b = wk.y * cols;
+    tl.p1 = 0;
+    tl.ncol = min(cols, d.n_p0 - tl.p0b);
+    // stage the prefetched rows; an Anderson iteration adds its other slots
+    const int nd = MODE == 0 ? C->n_d : 1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int c = w + WAVE_PENCILS * r;
+      if constexpr (MODE == 0) {
+        const R a0 = (R)C->alpha[0];
+        R v[U1];
+#pragma unroll
+        for (int u = 0; u < U1; ++u) v[u] = a0 * pre[r][u];
+        if (nd > 1 && c < tl.ncol) {
+          const uint32_t rowe = (uint32_t)(c * (int)d.in_s1 + j0);
+          for (int q = 1; q < nd; ++q) {
+            const R aq = (R)C->alpha[q];
+            const FM_GLOBAL char* src = (const FM_GLOBAL char*)gconst((const R*)d.ring) +
+                                        ((int64_t)C->slot_d[q] * d.ring_stride + (int64_t)tl.p0b * d.in_s1) *
+                                            (int64_t)sizeof(R);
+#pragma unroll
+            for (int u = 0; u < U1; ++u)
+              if (t + 64 * u < cnt) v[u] += aq * gld<R>(src, (rowe + (uint32_t)(t + 64 * u)) * (uint32_t)sizeof(R));
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U1; ++u)
+          if (t + 64 * u < cnt) sr[sidx<1>(c, t + 64 * u, pitch)] = v[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < U1; ++u)
+          if (t + 64 * u < cnt) {
+            if constexpr (cin) sc[sidx<1>(c, t + 64 * u, pitch)] = pre[r][u];
+            else sr[sidx<1>(c, t + 64 * u, pitch)] = pre[r][u];
+          }
+      }
+    }
+    __syncthreads();
+    const bool run = C->status == ST_RUNNING;
+    if (item + (int)gridDim.x < nwork) issue(item + gridDim.x);
+    if (run) {
+      const int outcnt = wave_pencil<R, MODE, 1, E>(d, KIND, n, packed, half, cols, w, t, mlane0, tl, j0, pitch,
+                                                    sr, sc, wscr, TwLds<R>{tw}, ltw, nogreen, nogz);
+      __syncthreads();
+      wave_store_x<R, MODE, 8>(d, C, tl, (int64_t)tl.p0b * d.out_s1, outcnt, cout_, eso, sr, sc, w, t);
     }
     __syncthreads();    // staging free for the next item
   }
