@@ -460,7 +460,7 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
 // Phase D of the x passes: output staging -> memory.  Forward: the
 // coefficient rows; inverse: u^f += w - sum_k beta_k delta_k and the new
 // increment into the ring (FP64 accumulator).
-template <typename R, int MODE, int UD>
+template <typename R, int MODE, int UD, int UX>
 __device__ __forceinline__ void wave_store_x(const PassDesc& d, const FM_GLOBAL Ctrl* C, const Tile& tl,
                                              int64_t out_blk, int outcnt, bool cout_, uint32_t eso, const R* sr,
                                              const cx<R>* sc, int w, int t) {
@@ -504,32 +504,40 @@ __device__ __forceinline__ void wave_store_x(const PassDesc& d, const FM_GLOBAL 
     FM_GLOBAL char* dw = (FM_GLOBAL char*)gmut((R*)d.ring) +
                          ((int64_t)C->slot_w * d.ring_stride + out_blk) * (int64_t)sizeof(R);
     FM_GLOBAL char* guf = (FM_GLOBAL char*)gmut(d.uf) + out_blk * (int64_t)sizeof(double);
-    constexpr int UX = 4;
-    for (int c = w; c < tl.ncol; c += WAVE_PENCILS) {
-      const uint32_t rowe = (uint32_t)(c * s1);
-      for (int eb = t; eb < outcnt; eb += UX * 64) {
-        R dl[UX];
-        double uo[UX];
+    // both rows of this wavefront: all loads first, then the stores
+    static_assert(2 * WAVE_PENCILS == 16, "two rows per wavefront");
+    for (int eb = t; eb < outcnt; eb += UX * 64) {
+      R dl[2][UX];
+      double uo[2][UX];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int c = w + WAVE_PENCILS * r;
+        const uint32_t rowe = (uint32_t)(c * s1);
 #pragma unroll
         for (int u = 0; u < UX; ++u) {
           const int e = eb + 64 * u;
-          if (e < outcnt) {
+          if (c < tl.ncol && e < outcnt) {
             const uint32_t o = rowe + (uint32_t)e;
             R a = sr[sidx<1>(c, e, opitch)];
 #pragma unroll
             for (int q = 0; q < MAX_DEPTH; ++q)
               if (q < nb) a -= be[q] * gld<R>(dsrc[q], o * (uint32_t)sizeof(R));
-            dl[u] = a;
-            uo[u] = gld<double>(guf, o * 8u);
+            dl[r][u] = a;
+            uo[r][u] = gld<double>(guf, o * 8u);
           }
         }
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int c = w + WAVE_PENCILS * r;
+        const uint32_t rowe = (uint32_t)(c * s1);
 #pragma unroll
         for (int u = 0; u < UX; ++u) {
           const int e = eb + 64 * u;
-          if (e < outcnt) {
+          if (c < tl.ncol && e < outcnt) {
             const uint32_t o = rowe + (uint32_t)e;
-            gst<R>(dw, o * (uint32_t)sizeof(R), dl[u]);
-            gst<double>(guf, o * 8u, uo[u] + (double)dl[u]);
+            gst<R>(dw, o * (uint32_t)sizeof(R), dl[r][u]);
+            gst<double>(guf, o * 8u, uo[r][u] + (double)dl[r][u]);
           }
         }
       }
@@ -729,7 +737,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   // ---------------- phase D: staging -> memory (coalesced) ----------------
   constexpr int UD = SK && !XP ? (CNT_OUT + STEP_C - 1) / STEP_C : 8;
   if (XP) {
-    wave_store_x<R, MODE, UD>(d, C, tl, out_blk, outcnt, cout_, eso, sr, sc, w, t);
+    wave_store_x<R, MODE, UD, SK ? (CNT_OUT + 63) / 64 : 4>(d, C, tl, out_blk, outcnt, cout_, eso, sr, sc, w, t);
   } else {
     FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) + out_blk * (int64_t)eso;
     const int opitch = cols + 1;
@@ -1040,7 +1048,7 @@ __global__ void __launch_bounds__(WAVE_THREADS, (KIND == K_DFT || MODE == 1) ? 1
       const int outcnt = wave_pencil<R, MODE, 1, E>(d, KIND, n, packed, half, cols, w, t, mlane0, tl, j0, pitch,
                                                     sr, sc, wscr, TwLds<R>{tw}, ltw, nogreen, nogz);
       __syncthreads();
-      wave_store_x<R, MODE, 8>(d, C, tl, (int64_t)tl.p0b * d.out_s1, outcnt, cout_, eso, sr, sc, w, t);
+      wave_store_x<R, MODE, 8, (n + 1 + 63) / 64>(d, C, tl, (int64_t)tl.p0b * d.out_s1, outcnt, cout_, eso, sr, sc, w, t);
     }
     __syncthreads();    // staging free for the next item
   }
