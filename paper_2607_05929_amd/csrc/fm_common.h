@@ -140,7 +140,6 @@ struct PassDesc {
   // Green (fused z pass): per-axis tables of this component
   const double* gs2[3];           // sin^2(xi/2) per spectral index
   const double* gc2[3];           // cos^2(xi/2)
-  const uint8_t* gfl[3];          // bit0: xi = 0, bit1: xi = pi
   int32_t scheme, green_lam;      // green_lam: 1 uses lambda0 (B0), 0 for 2mu0
   double h, lam0, mu0;
 };

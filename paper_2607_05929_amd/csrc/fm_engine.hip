@@ -209,7 +209,7 @@ struct Layout {
   size_t ctrl, log, uf, Dring, dring, specA, specB, mat, mlaw, mtab, state, part_s, part_d, part_g,
       tw, gtab, group, total;
   size_t tw_off[3][3];
-  size_t g_off[3][3];   // green tables per comp, axis: s2 (M doubles), c2 (M doubles), flags (M bytes)
+  size_t g_off[3][3];   // green tables per comp, axis: s2 (M doubles), c2 (M doubles)
   size_t group_bytes;
 };
 
@@ -264,7 +264,7 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
   for (int q = 0; q < 3; ++q)
     for (int a = 0; a < 3; ++a) L.tw_off[q][a] = take(2 * R * (size_t)g.L[q][a]);
   for (int q = 0; q < 3; ++q)
-    for (int a = 0; a < 3; ++a) L.g_off[q][a] = take(17 * (size_t)g.M[q][a]);
+    for (int a = 0; a < 3; ++a) L.g_off[q][a] = take(16 * (size_t)g.M[q][a]);
   // sized for the most tiles any transform-kernel choice can produce (one
   // column per tile), so that fm_autotune can switch kernels in place
   Geometry gmax = g;
@@ -539,7 +539,6 @@ void fill_pass_descs(fm_plan* p) {
             char* t = ws + p->lay.g_off[q][a];
             d.gs2[a] = (const double*)t;
             d.gc2[a] = (const double*)(t + 8 * (size_t)g.M[q][a]);
-            d.gfl[a] = (const uint8_t*)(t + 16 * (size_t)g.M[q][a]);
           }
           d.scheme = p->d.scheme;
           d.green_lam = p->d.green == FM_GREEN_B0;
@@ -573,12 +572,12 @@ int upload_tables(fm_plan* p) {
         HIPCHK(hipMemcpyAsync(ws + p->lay.tw_off[q][a], t.data(), 4 * t.size(), hipMemcpyHostToDevice, p->stream));
         HIPCHK(hipStreamSynchronize(p->stream));
       }
-      // Green tables: sin^2(xi/2), cos^2(xi/2) and index flags (xi = 0, xi = pi)
+      // Green tables: sin^2(xi/2), cos^2(xi/2), exact 0 / 1 at the index-flagged
+      // frequencies xi = 0 and xi = pi (the null-mode rule relies on it)
       const int M = g.M[q][a], n = g.n[a], k = g.kinds[q][a];
-      std::vector<char> buf(17 * (size_t)M);
+      std::vector<char> buf(16 * (size_t)M);
       double* s2 = (double*)buf.data();
       double* c2 = s2 + M;
-      uint8_t* fl = (uint8_t*)(c2 + M);
       for (int i = 0; i < M; ++i) {
         long double xi;
         switch (k) {
@@ -595,7 +594,6 @@ int upload_tables(fm_plan* p) {
         if (f & 2) { s = 1; c = 0; }
         s2[i] = (double)(s * s);
         c2[i] = (double)(c * c);
-        fl[i] = f;
       }
       HIPCHK(hipMemcpyAsync(ws + p->lay.g_off[q][a], buf.data(), buf.size(), hipMemcpyHostToDevice, p->stream));
       HIPCHK(hipStreamSynchronize(p->stream));

@@ -26,25 +26,6 @@ namespace fm {
 constexpr int PASS_THREADS = 1024;
 constexpr int PASS_MAXPTS = 7680;      // F * L bound for register staging
 
-// Green factor 1/den at spectral indices (k0, k1, k2) of component q:
-// den = (4/h^2)(2 mu0 sum_i t_i + lambda0 t_q), Eqs. NSGO2_HEX1 / NSGO2_TETRA2
-// with t_i the squared modified-frequency components built from the 1D
-// sin^2 / cos^2 tables; 0 on the null modes (decided from index flags).
-__device__ __forceinline__ double green_factor(const PassDesc& d, int k0, int k1, int k2) {
-  const uint8_t f0 = d.gfl[0][k0], f1 = d.gfl[1][k1], f2 = d.gfl[2][k2];
-  const int allz = (f0 & f1 & f2) & 1;
-  const int npi = ((f0 >> 1) & 1) + ((f1 >> 1) & 1) + ((f2 >> 1) & 1);
-  if (allz) return 0.0;
-  if (d.scheme == 0 ? (npi >= 2) : (npi == 3)) return 0.0;
-  const double s0 = d.gs2[0][k0], s1 = d.gs2[1][k1], s2 = d.gs2[2][k2];
-  const double c0 = d.gc2[0][k0], c1 = d.gc2[1][k1], c2 = d.gc2[2][k2];
-  double t0 = s0 * c1 * c2, t1 = c0 * s1 * c2, t2 = c0 * c1 * s2;
-  if (d.scheme == 1) { t0 += c0 * s1 * s2; t1 += s0 * c1 * s2; t2 += s0 * s1 * c2; }
-  const double tq = d.q == 0 ? t0 : (d.q == 1 ? t1 : t2);
-  const double den = (4.0 / (d.h * d.h)) * (2.0 * d.mu0 * (t0 + t1 + t2) + (d.green_lam ? d.lam0 * tq : 0.0));
-  return 1.0 / den;
-}
-
 // LDS position of element e of a pencil (identity; a padded layout costs
 // more registers than its bank-conflict savings in this kernel).
 __device__ __forceinline__ int PD(int e) { return e; }

@@ -58,8 +58,10 @@ def test_green_apply(B, prec, seed, n, scheme, green):
 
 
 # Grids whose pencil lengths L = 64 E reach every wavefront-kernel variant
-# (E = 1, 2, 3, 4, 5, 6, 8, 12) on the x, y and z axes, for each transform kind.
-WAVE_SHAPES = [(256, 6, 5), (6, 256, 5), (5, 6, 256), (96, 160, 6), (192, 7, 128), (64, 32, 384)]
+# (E = 1, 2, 3, 4, 5, 6, 8, 12) on the x, y and z axes, for each transform kind;
+# the 512-point DFT shapes reach the E = 8 periodic (r2c and complex) kernels.
+WAVE_SHAPES = [(256, 6, 5), (6, 256, 5), (5, 6, 256), (96, 160, 6), (192, 7, 128), (64, 32, 384),
+               (512, 5, 6), (6, 512, 5), (5, 6, 512)]
 BC_PATTERNS = {
     "P": [W.P, W.P], "N": [W.N, W.N], "D": [W.D, W.D], "ND": [W.N, W.D], "DN": [W.D, W.N],
 }

@@ -134,6 +134,8 @@ def test_batch_equals_alone(B):
     res = B.batch_solve(probs, fields=True)
     for p, r in zip(probs, res):
         alone = B.solve(p, prec=W.FP32_MIXED)
+        print(f"long-pencil member n={p.n} rc {r['rc']} iters {r['iters']} alone {alone['iters']} "
+              f"{alone['converged']}", flush=True)
         assert r["rc"] == 0
         assert r["iters"] == alone["iters"]
         np.testing.assert_array_equal(r["sig"], alone["sig"])
@@ -144,6 +146,41 @@ def test_batch_equals_alone(B):
         e = rel_err(res[k]["macro_sigma"], ref["macro_sigma"])
         print(f"batch member {k} macro err vs oracle {e:.2e}", flush=True)
         assert e < 1e-5
+
+
+def test_batch_long_pencils_equals_alone(B):
+    """A batch whose solves put 512-point pencils on different axes: the
+    persistent pipelined pass kernels take work items of several solves in
+    one launch; every member equals its own solve bitwise, and the oracle.
+    (These thin grids converge slowly; their FP32 error floor lies between
+    1e-6 and 1e-5, so the FP32 solves stop at 1e-5 and the oracle, solved to
+    1e-8, is matched to 1e-4 on the macroscopic stress.)"""
+    rng = np.random.default_rng(21)
+    shapes = [(256, 6, 5), (6, 256, 5), (5, 6, 256), (6, 256, 6)]
+    probs = []
+    for k, sh in enumerate(shapes):
+        p = W.random_small_problem(rng, n=sh, scheme=(W.HEX1, W.TETRA2)[k % 2], tol=1e-5,
+                                   law=("iso", "cubic")[k % 2], prec=W.FP32_MIXED)
+        p.max_iter = 2000
+        long_ax = int(np.argmax(sh))
+        for q in range(3):
+            # N/N (DCT-I) or D/D (DST-I) on the long axis: 512-point pencils
+            p.bc[q][long_ax] = [W.N, W.N] if (q + k) % 2 == 0 else [W.D, W.D]
+        probs.append(p)
+    res = B.batch_solve(probs, fields=True)
+    for p, r in zip(probs, res):
+        alone = B.solve(p, prec=W.FP32_MIXED)
+        print(f"long-pencil member n={p.n} rc {r['rc']} iters {r['iters']} alone {alone['iters']} "
+              f"{alone['converged']}", flush=True)
+        assert r["rc"] == 0
+        assert r["iters"] == alone["iters"]
+        np.testing.assert_array_equal(r["sig"], alone["sig"])
+    for k in (0, 2):
+        probs[k].tol = 1e-8
+        ref = osolver.solve(probs[k])
+        e = rel_err(res[k]["macro_sigma"], ref["macro_sigma"])
+        print(f"long-pencil batch member {k} macro err vs oracle {e:.2e}", flush=True)
+        assert e < 1e-4
 
 
 def test_server_mix_equals_alone(B):
