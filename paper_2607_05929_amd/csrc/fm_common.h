@@ -103,6 +103,7 @@ struct SolveDev {
   const void* mtab;       // material table, MT_STRIDE reals per entry
   const int32_t* mlaw;    // law per material
   void* state;            // 7 * nppv * Nv reals (or null)
+  void* sig;              // plastic solves: stress of the iterate, 6 * nppv * Nv reals (or null)
   Ctrl* ctrl;
   LogEntry* log;
   double* part_s;         // ntile_s * NPART_S (stress-divergence tiles)

@@ -206,7 +206,7 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
 
 // Layout of a plan workspace: offsets of every buffer.
 struct Layout {
-  size_t ctrl, log, uf, Dring, dring, specA, specB, mat, mlaw, mtab, state, part_s, part_d, part_g,
+  size_t ctrl, log, uf, Dring, dring, specA, specB, mat, mlaw, mtab, state, sig, part_s, part_d, part_g,
       tw, gtab, group, total;
   size_t tw_off[3][3];
   size_t g_off[3][3];   // green tables per comp, axis: s2 (M doubles), c2 (M doubles)
@@ -258,6 +258,7 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
   L.mlaw = take(4 * (size_t)d->max_materials);
   L.mtab = take(R * MT_STRIDE * (size_t)d->max_materials);
   L.state = d->with_state ? take(R * 7 * g.nppv * (size_t)g.Nv) : 0;
+  L.sig = d->with_state ? take(R * 6 * g.nppv * (size_t)g.Nv) : 0;
   L.part_s = take(8 * NPART_S * (size_t)g.ntile_s);
   L.part_d = take(8 * (size_t)g.ntile_d);
   L.part_g = take(8 * NGRAM * (size_t)g.ntile_d);
@@ -963,8 +964,13 @@ int launch_one(const Group& G, int k) {
   switch (k) {
     case 0:
       if (!G.nwl[7]) break;
-      if (G.plastic)
+      if (G.plastic) {
+        // plastic solves: the law once per voxel (one thread each), then the
+        // fused kernel reads those stresses
+        if (G.nwl[0])
+          hipLaunchKernelGGL((k_commit<R, 1, 1>), dim3(G.nwl[0] * (SPACE_TILE / 256)), dim3(256), 0, st, G.S, G.wl[0]);
         hipLaunchKernelGGL((k_sdiv<R, 1>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[7]);
+      }
       else
         hipLaunchKernelGGL((k_sdiv<R, 0>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[7]);
       break;
@@ -1256,6 +1262,7 @@ int fm_plan_create(const fm_plan_desc* desc, void* d_workspace, size_t ws_bytes,
   s.mtab = ws + p->lay.mtab;
   s.mlaw = (const int32_t*)(ws + p->lay.mlaw);
   s.state = desc->with_state ? ws + p->lay.state : nullptr;
+  s.sig = desc->with_state ? ws + p->lay.sig : nullptr;
   s.ctrl = (Ctrl*)(ws + p->lay.ctrl);
   s.log = (LogEntry*)(ws + p->lay.log);
   s.part_s = (double*)(ws + p->lay.part_s);

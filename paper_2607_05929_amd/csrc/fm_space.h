@@ -169,13 +169,18 @@ __device__ __forceinline__ void voxel_strain(const SolveDev& s, const FM_GLOBAL 
 
 // Commit of an increment: behaviour law with the converged strain, internal
 // variables stored, FP64 strain / stress outputs.  PL = 0 compiles the
-// elastic laws only, PL = 1 all laws.
-template <typename R, int PL>
+// elastic laws only, PL = 1 all laws.  SIGMA = 1 is the stress pass of an
+// iteration of a plastic solve instead: one voxel per thread (four blocks
+// per voxel tile), the law with the internal variables of the previous
+// increment, the stress into the solve's stress buffer, nothing else written.
+template <typename R, int PL, int SIGMA = 0>
 __global__ void __launch_bounds__(256) k_commit(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
-  const int2 w = work[blockIdx.x];
+  const int2 w = work[SIGMA ? blockIdx.x / (SPACE_TILE / 256) : blockIdx.x];
   const SolveDev& s = S[w.x];
   const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
-  for (int sub = 0; sub < SPACE_TILE / 256; ++sub) {
+  if (SIGMA && (s.sig == nullptr || C->status != ST_RUNNING)) return;
+  for (int sub = SIGMA ? (int)(blockIdx.x % (SPACE_TILE / 256)) : 0; sub < SPACE_TILE / 256;
+       sub += SIGMA ? SPACE_TILE / 256 : 1) {
     const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
     if (v >= s.Nv) continue;
     const int n0 = s.n[0], n1 = s.n[1];
@@ -200,6 +205,11 @@ __global__ void __launch_bounds__(256) k_commit(const SolveDev* __restrict__ S, 
       R sig[6];
       if (PL) law_eval_f64<R>(law, P, eps[r], sig, st, stn, C->dt);
       else law_elastic<R>(law, P, eps[r], sig, st, stn);
+      if (SIGMA) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) gmut((R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v] = sig[k];
+        continue;
+      }
       if (PL && s.has_state && (law == LAW_J2 || law == LAW_CP)) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) state[((int64_t)k * s.nppv + r) * s.Nv + v] = stn[k];
@@ -224,9 +234,10 @@ __global__ void __launch_bounds__(256) k_commit(const SolveDev* __restrict__ S, 
 // that there are enough blocks to fill the GPU).
 // It marches up the layers: for voxel layer z it evaluates the behaviour law
 // on the 32 x 8 voxels that touch the tile (one per thread, the tile plus a
-// one-voxel halo) into an LDS ring of two voxel layers, then forms the
-// divergence at node layer z from voxel layers z-1 and z.  The stress never
-// goes to memory.  Outside the grid a halo voxel holds the periodic image
+// one-voxel halo; plastic solves read them from their per-voxel stress pass
+// instead), sums each voxel column's contributions of layers z-1 and z into
+// LDS partials, then forms the divergence at node layer z.  The stress of an
+// elastic solve never goes to memory.  Outside the grid a halo voxel holds the periodic image
 // along axes periodic for some component, and zero otherwise (see
 // node_div for the reflecting faces).  Every voxel's stress enters the
 // block partials (sum w |sigma|^2, sum sigma) exactly once, in the tile that
@@ -400,6 +411,8 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
 #pragma unroll
     for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k] = 0;
   const NodeXY<R> nxy = node_xy<R>(s, J0, J1);
+  // plastic solves read the stresses of the per-voxel stress pass
+  const bool from_buf = PL && s.sig != nullptr;
   // FP32 corner carry: top corner 4 (FP64) and corners 5-7 minus it, per component
   double cu4[3] = {0, 0, 0};
   R cdt[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -417,7 +430,7 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
       const int law = gconst(s.mlaw)[mt_cur];
       const FM_GLOBAL R* P = gconst((const R*)s.mtab) + (int64_t)mt_cur * MT_STRIDE;
       R eps[2][6];
-      {
+      if (!from_buf) {
         R u[3][8], gs[3][3];
         if constexpr (sizeof(R) == 4) {
           // FP32: FP64 differences to corner 0, with the bottom face taken
@@ -464,16 +477,21 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
       const bool zero_halo = zero_xy || (!s.wrap[2] && (zl < 0 || zl >= n2));
       for (int r = 0; r < s.nppv; ++r) {
         R st[7], stn[7], sig[6];
-        if (PL && s.has_state) {
-          const FM_GLOBAL R* state = gconst((const R*)s.state);
+        if (PL && from_buf) {
 #pragma unroll
-          for (int k = 0; k < 7; ++k) st[k] = state[((int64_t)k * s.nppv + r) * s.Nv + v];
+          for (int k = 0; k < 6; ++k) sig[k] = gconst((const R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v];
         } else {
+          if (PL && s.has_state) {
+            const FM_GLOBAL R* state = gconst((const R*)s.state);
 #pragma unroll
-          for (int k = 0; k < 7; ++k) st[k] = 0;
+            for (int k = 0; k < 7; ++k) st[k] = state[((int64_t)k * s.nppv + r) * s.Nv + v];
+          } else {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) st[k] = 0;
+          }
+          if (PL) law_eval_f64<R>(law, P, eps[r], sig, st, stn, C->dt);
+          else law_elastic<R>(law, P, eps[r], sig, st, stn);
         }
-        if (PL) law_eval_f64<R>(law, P, eps[r], sig, st, stn, C->dt);
-        else law_elastic<R>(law, P, eps[r], sig, st, stn);
         // halo voxels across faces of axes periodic for no component hold zero
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
