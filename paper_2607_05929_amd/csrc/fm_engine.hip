@@ -190,11 +190,10 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   g.sd_nt[0] = (int)cdiv(g.N[0], SD_TX);
   g.sd_nt[1] = (int)cdiv(g.N[1], SD_TY);
   // Layers per tile: SD_ZC, halved while the grid gives fewer than 8 blocks
-  // per compute unit (1 for the plastic laws, whose kernel holds one or two
-  // blocks per compute unit and whose per-layer cost is high): each tile
-  // recomputes one voxel layer below it, so fewer layers cost more law
-  // evaluations but fill the GPU on small grids.
-  const int64_t want = (d->with_state ? 1 : 8) * 256;
+  // per compute unit: each tile recomputes one voxel layer below it, so fewer
+  // layers cost more law evaluations (elastic ones: plastic solves read
+  // their stresses from the stress pass) but fill the GPU on small grids.
+  const int64_t want = 8 * 256;
   g.sd_zc = SD_ZC;
   while (g.sd_zc > 1 && (int64_t)g.sd_nt[0] * g.sd_nt[1] * cdiv(g.N[2], g.sd_zc) < want) g.sd_zc /= 2;
   g.sd_nt[2] = (int)cdiv(g.N[2], g.sd_zc);

@@ -361,8 +361,11 @@ __device__ __forceinline__ void node_div(const R* __restrict__ P, int lx, int ly
 // Bytes of dynamic LDS of k_sdiv.
 __host__ __device__ inline size_t sdiv_lds_bytes(int rbytes) { return (size_t)12 * SD_VT * rbytes; }
 
+// PL = 1: the group holds solves with internal variables, whose stresses
+// come from the stress pass (k_commit with SIGMA = 1); the law evaluated here
+// is elastic.
 template <typename R, int PL>
-__global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
+__global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
   const SolveDev& s = S[w.x];
   const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
@@ -476,21 +479,16 @@ __global__ void __launch_bounds__(256, (PL || sizeof(R) == 8) ? 1 : 4) k_sdiv(co
       const bool own = own_xy && zl >= Z0 && zl < n2;
       const bool zero_halo = zero_xy || (!s.wrap[2] && (zl < 0 || zl >= n2));
       for (int r = 0; r < s.nppv; ++r) {
-        R st[7], stn[7], sig[6];
-        if (PL && from_buf) {
+        R sig[6];
+        if (from_buf) {
 #pragma unroll
           for (int k = 0; k < 6; ++k) sig[k] = gconst((const R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v];
         } else {
-          if (PL && s.has_state) {
-            const FM_GLOBAL R* state = gconst((const R*)s.state);
+          // solves without internal variables: elastic laws only
+          R st[7], stn[7];
 #pragma unroll
-            for (int k = 0; k < 7; ++k) st[k] = state[((int64_t)k * s.nppv + r) * s.Nv + v];
-          } else {
-#pragma unroll
-            for (int k = 0; k < 7; ++k) st[k] = 0;
-          }
-          if (PL) law_eval_f64<R>(law, P, eps[r], sig, st, stn, C->dt);
-          else law_elastic<R>(law, P, eps[r], sig, st, stn);
+          for (int k = 0; k < 7; ++k) st[k] = 0;
+          law_elastic<R>(law, P, eps[r], sig, st, stn);
         }
         // halo voxels across faces of axes periodic for no component hold zero
 #pragma unroll
