@@ -363,10 +363,13 @@ def solve(prob, prec=None, fields=True, log_capacity=0):
         p.close()
 
 
-def batch_solve(problems, prec=None, fields=False):
-    """Solve independent problems together (fm_batch_solve)."""
+def batch_solve(problems, prec=None, fields=False, plans=None):
+    """Solve independent problems together (fm_batch_solve).  `plans`:
+    already created plans of the problems (kept open), else created here."""
     torch = _torch()
-    plans = [Plan(p, prec) for p in problems]
+    own = plans is None
+    if own:
+        plans = [Plan(p, prec) for p in problems]
     n = len(plans)
     handles = (C.c_void_p * n)(*[p.handle.value for p in plans])
     steps = [load_steps(p.steps) for p in problems]
@@ -397,8 +400,9 @@ def batch_solve(problems, prec=None, fields=False):
             r["sig"] = bufs[i]["sig"].cpu().numpy().reshape(6, pl.nppv, n3, n2, n1)
             r["eps"] = bufs[i]["eps"].cpu().numpy().reshape(6, pl.nppv, n3, n2, n1)
         res.append(r)
-    for pl in plans:
-        pl.close()
+    if own:
+        for pl in plans:
+            pl.close()
     return res
 
 
