@@ -183,7 +183,9 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
     }
   }
   const R ihs = (R)1 / (taus - tau0), iesc = (R)1 / escale;
-  auto resid = [&](const R* sg, R d, R* Rs, R& Rg, R* gd, R& tc) -> R {
+  // slip rate of system s_ at resolved shear ratio r
+  auto rate = [&](R r) { return g0 * powabs(r, nx) * (r < 0 ? (R)-1 : (R)1); };
+  auto resid = [&](const R* sg, R d, R* Rs, R& Rg, R& tc) -> R {
     tc = tau0 + (taus - tau0) * (1 - exp(-th0 * (Gn + d) * ihs));
     const R itc = (R)1 / tc;
     R eps_s[6];
@@ -193,9 +195,7 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
     R sum = 0;
 #pragma unroll
     for (int s_ = 0; s_ < 12; ++s_) {
-      const R r = tau_of(sg, s_) * itc;
-      const R g = g0 * powabs(r, nx) * (r < 0 ? (R)-1 : (R)1);
-      gd[s_] = g;
+      const R g = rate(tau_of(sg, s_) * itc);
       sum += fabs(g);
 #pragma unroll
       for (int i = 0; i < 6; ++i) Rs[i] += dt * g * schmid_c<R>(s_, i);
@@ -206,8 +206,9 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
     for (int i = 0; i < 6; ++i) nr = fmax(nr, fabs(Rs[i]));
     return nr * iesc;
   };
-  R Rs[6], Rg, gd[12], tc;
-  R nr = resid(sig, dG, Rs, Rg, gd, tc);
+  // (the slip rates are recomputed where needed rather than kept: registers)
+  R Rs[6], Rg, tc;
+  R nr = resid(sig, dG, Rs, Rg, tc);
   for (int it = 0; it < 80 && nr >= LawTol<R>::cp; ++it) {
     R J[7][8];
     const R hG = th0 * exp(-th0 * (Gn + dG) * ihs);
@@ -223,9 +224,11 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
 #pragma unroll
     for (int s_ = 0; s_ < 12; ++s_) {
       const R r = tau_of(sig, s_) * itc;
-      const R a = nx * g0 * powabs(r, nx - 1) * itc;
+      const R pw = powabs(r, nx - 1);
+      const R a = nx * g0 * pw * itc;
       const R sg = r < 0 ? (R)-1 : (R)1;
-      const R ca = dt * a, cb = dt * nx * gd[s_] * itc * hG, cc = dt * sg * a;
+      const R gs = g0 * pw * fabs(r) * sg;          // slip rate g0 |r|^n sign r
+      const R ca = dt * a, cb = dt * nx * gs * itc * hG, cc = dt * sg * a;
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         const R pi = schmid_c<R>(s_, i);
@@ -234,7 +237,7 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
         J[i][6] -= cb * pi;
         J[6][i] -= cc * pi;
       }
-      J[6][6] += dt * nx * fabs(gd[s_]) * itc * hG;
+      J[6][6] += dt * nx * fabs(gs) * itc * hG;
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) J[i][7] = Rs[i];
@@ -271,13 +274,13 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
       dx[p] = t * ipv[p];
     }
     R lam = 1;
-    R s_new[6], d_new, Rs2[6], Rg2, gd2[12], tc2, nr2 = nr;
+    R s_new[6], d_new, Rs2[6], Rg2, tc2, nr2 = nr;
     bool improved = false;
     for (int ls = 0; ls < 30; ++ls) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) s_new[i] = sig[i] - lam * dx[i];
       d_new = fmax(dG - lam * dx[6], (R)0);
-      nr2 = resid(s_new, d_new, Rs2, Rg2, gd2, tc2);
+      nr2 = resid(s_new, d_new, Rs2, Rg2, tc2);
       if (nr2 < nr) { improved = true; break; }
       if (lam < (R)1e-7) break;
       lam *= (R)0.5;
@@ -288,17 +291,17 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
 #pragma unroll
     for (int i = 0; i < 6; ++i) { sig[i] = s_new[i]; Rs[i] = Rs2[i]; }
     dG = d_new; Rg = Rg2; tc = tc2; nr = nr2;
-#pragma unroll
-    for (int s_ = 0; s_ < 12; ++s_) gd[s_] = gd2[s_];
   }
   // back to the sample frame: stress and plastic strain increment
-  R dp[6];
+  R dp[6] = {0, 0, 0, 0, 0, 0};
+  {
+    const R itc = (R)1 / tc;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    R e = 0;
+    for (int s_ = 0; s_ < 12; ++s_) {
+      const R g = rate(tau_of(sig, s_) * itc);
 #pragma unroll
-    for (int s_ = 0; s_ < 12; ++s_) e += dt * gd[s_] * schmid_c<R>(s_, i);
-    dp[i] = e;
+      for (int i = 0; i < 6; ++i) dp[i] += dt * g * schmid_c<R>(s_, i);
+    }
   }
   mandel_rotate<R>(Rm, sig, sm, false);
   R dps[6];

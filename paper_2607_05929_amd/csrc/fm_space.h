@@ -174,7 +174,7 @@ __device__ __forceinline__ void voxel_strain(const SolveDev& s, const FM_GLOBAL 
 // per voxel tile), the law with the internal variables of the previous
 // increment, the stress into the solve's stress buffer, nothing else written.
 template <typename R, int PL, int SIGMA = 0>
-__global__ void __launch_bounds__(256) k_commit(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
+__global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
   const int2 w = work[SIGMA ? blockIdx.x / (SPACE_TILE / 256) : blockIdx.x];
   const SolveDev& s = S[w.x];
   const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
