@@ -94,7 +94,10 @@ typedef struct {
   double  lambda0, mu0;    /* reference medium (Eq. FourierNSGO2) */
   int32_t prec;            /* FM_FP64 or FM_FP32_MIXED */
   double  tol;             /* equilibrium tolerance (Eq. equilibrium_condition) */
-  int32_t max_iter;        /* iteration cap per load increment */
+  int32_t max_iter;        /* iteration cap per load increment; an increment also stops,
+                              not converged, when its error has not fallen below 0.99 of
+                              its best for 200 iterations while within 100 tol (the
+                              rounding floor of the precision) */
   int32_t aa_depth;        /* Anderson history depth, 1..4 (1 disables) */
   int32_t aa_period;       /* Anderson applied when m >= 2 and m % period == 0 */
   int32_t max_materials;   /* capacity of the material table */
@@ -173,7 +176,7 @@ int fm_set_material(fm_plan* plan, const int32_t* d_mat_id, int32_t n_mat,
                     const fm_material* table);
 
 /* Run the load path (Alg. 1, all increments) from the current state.
- * Returns FM_OK, FM_W_NOT_CONVERGED (some increment hit max_iter), or an
+ * Returns FM_OK, FM_W_NOT_CONVERGED (some increment hit max_iter or stagnated), or an
  * error.  log may be NULL; entries beyond its capacity are dropped. */
 int fm_solve(fm_plan* plan, const fm_load_step* steps, int32_t n_steps,
              fm_outputs* out, fm_iter_log* log);

@@ -52,10 +52,12 @@ struct Ctrl {
   int32_t log_count;
   int32_t max_iter, depth, period;
   int32_t mixed_mask[6];
-  int32_t pad_[3];
+  int32_t best_m;         // iterate of the smallest error so far (this increment)
+  int32_t pad_[2];
   double alpha[MAX_DEPTH];
   double beta[MAX_DEPTH];
   double err, sumD2, sumS2;
+  double best_err;        // smallest error so far (this increment)
   double macro[6];
   double c[3];
   double G[9];            // G[q*3+l]

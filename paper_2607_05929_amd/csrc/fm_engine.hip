@@ -1065,6 +1065,8 @@ int begin_step(fm_plan* p, const fm_load_step& st, int t, const Ctrl* prev) {
   std::memset(&c, 0, sizeof(c));
   c.m = 0;
   c.status = ST_RUNNING;
+  c.best_err = INFINITY;
+  c.best_m = 0;
   c.step = t;
   c.max_iter = p->d.max_iter;
   c.depth = p->d.aa_depth;

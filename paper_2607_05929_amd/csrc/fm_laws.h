@@ -391,29 +391,25 @@ __device__ __forceinline__ void law_eval(int law, PT P, const R eps[6], R sig[6]
   }
 }
 
-// Plastic laws evaluated in FP64 whatever the storage precision.  The flow
-// rule's power law (exponent n = 20 in the FCC workloads) amplifies the
-// rounding of a resolved shear n-fold, so an FP32 return mapping only
-// reaches ~1e-6 relative accuracy, the size of the equilibrium tolerance,
-// and its stress is not a smooth function of the strain at that level; in
-// FP64 it is, and the FP32 solve converges as the FP64 one does.
+// Plastic laws are evaluated in FP64 from an FP64 strain whatever the
+// storage precision (internal variables and the stress are stored in R).
+// The flow rule's power law (exponent n = 20 in the FCC workloads) amplifies
+// the rounding of a resolved shear n-fold, so an FP32 return mapping only
+// reaches ~1e-6 relative accuracy, the size of the equilibrium tolerance; and
+// the yield / flow switches of a law fed an FP32 strain flip between
+// iterations on its rounding.  Both stall the FP32 solve; in FP64 the stress
+// is a smooth function of u^f and the FP32 solve converges as the FP64 one.
 template <typename R, typename PT>
-__device__ __forceinline__ void law_eval_f64(int law, PT P, const R eps[6], R sig[6], const R st[7], R stn[7],
+__device__ __forceinline__ void law_eval_e64(int law, PT P, const double eps[6], R sig[6], const R st[7], R stn[7],
                                              double dt) {
-  if constexpr (sizeof(R) == 8) {
-    law_eval<double>(law, P, eps, sig, st, stn, dt);
-  } else {
-    double e[6], s[6], a[7], b[7];
+  double s[6], a[7], b[7];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) e[i] = eps[i];
+  for (int i = 0; i < 7; ++i) a[i] = st[i];
+  law_eval<double>(law, P, eps, s, a, b, dt);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) a[i] = st[i];
-    law_eval<double>(law, P, e, s, a, b, dt);
+  for (int i = 0; i < 6; ++i) sig[i] = (R)s[i];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) sig[i] = (R)s[i];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) stn[i] = (R)b[i];
-  }
+  for (int i = 0; i < 7; ++i) stn[i] = (R)b[i];
 }
 
 }  // namespace fm

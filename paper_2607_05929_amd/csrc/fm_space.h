@@ -22,6 +22,7 @@
 
 namespace fm {
 
+constexpr int STALL_ITERS = 200;   // iterations without a 1 % better error (stagnation)
 constexpr int SPACE_TILE = 1024;   // voxels / nodes per 256-thread block (4 per thread)
 
 __device__ __forceinline__ int vidx(int l, int q) {
@@ -187,8 +188,12 @@ __global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* _
     const int x = (int)(v % n0);
     const int64_t t = v / n0;
     const int y = (int)(t % n1), z = (int)(t / n1);
-    R eps[2][6];
-    voxel_strain<R>(s, C, x, y, z, eps);
+    // plastic laws take an FP64 strain: their yield / flow switches must not
+    // see the rounding of an FP32 strain, which makes them chatter between
+    // iterations and stalls the FP32 solve
+    typedef typename std::conditional<PL != 0, double, R>::type E;
+    E eps[2][6];
+    voxel_strain<E>(s, C, x, y, z, eps);
     const int mt = gconst(s.mat)[v];
     const int law = gconst(s.mlaw)[mt];
     const FM_GLOBAL R* P = gconst((const R*)s.mtab) + (int64_t)mt * MT_STRIDE;
@@ -203,7 +208,7 @@ __global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* _
         for (int k = 0; k < 7; ++k) st[k] = 0;
       }
       R sig[6];
-      if (PL) law_eval_f64<R>(law, P, eps[r], sig, st, stn, C->dt);
+      if constexpr (PL != 0) law_eval_e64<R>(law, P, eps[r], sig, st, stn, C->dt);
       else law_elastic<R>(law, P, eps[r], sig, st, stn);
       if (SIGMA) {
 #pragma unroll
@@ -625,6 +630,17 @@ __global__ void __launch_bounds__(256) k_control(const SolveDev* __restrict__ S,
   }
   if (err < C->tol && mixed_ok) { C->status = ST_CONVERGED; return; }
   if (m >= C->max_iter) { C->status = ST_MAXITER; return; }
+  // Stagnation: an error that has not fallen below 0.99 of its best for
+  // STALL_ITERS iterations while within 100 tol sits at the rounding floor of
+  // the precision (FP32 on slowly converging problems); the increment stops
+  // there, reported as not converged, instead of running to max_iter.
+  if (err < 0.99 * C->best_err) {
+    C->best_err = err;
+    C->best_m = m;
+  } else if (m - C->best_m >= STALL_ITERS && err < 100.0 * C->tol) {
+    C->status = ST_MAXITER;
+    return;
+  }
   if (ns > 0) {
     // Voigt C0 block on the stress-controlled components, solved by Gauss elimination
     double Mx[6][7];
