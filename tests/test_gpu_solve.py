@@ -96,6 +96,23 @@ def test_j2_mixed_fp32(B):
     assert e < 1e-5
 
 
+def test_j2_fp32_converges_like_fp64(B):
+    """Precision policy for plastic solves: with the FP64 strain and law the
+    FP32-mixed path converges in about the FP64 iteration counts (an FP32
+    strain made the yield switch chatter and the increments stall), and the
+    macroscopic stress agrees with the FP64 path."""
+    prob = W.config_j2_inclusions(nv=96, n_steps=6, eps_final=6e-3)
+    r32 = B.solve(prob, prec=W.FP32_MIXED, fields=False)
+    r64 = B.solve(prob, prec=W.FP64, fields=False)
+    print(f"j2 96^3 iters fp32 {r32['iters']} fp64 {r64['iters']}", flush=True)
+    assert all(r32["converged"]) and all(r64["converged"])
+    for a, b in zip(r32["iters"], r64["iters"]):
+        assert a <= 1.5 * b + 10
+    zz32, zz64 = r32["macro_sigma"][:, 2], r64["macro_sigma"][:, 2]
+    assert rel_err(zz32, zz64) < 1e-5
+    assert np.abs(r32["macro_sigma"][:, :2]).max() < 1e-5 * np.abs(zz64).max()
+
+
 def _cp_problem(prec):
     rng = np.random.default_rng(55)
     prob = W.cp_polycrystal(rng, 8, 4, prec=prec, n_steps=3, eps_max=4e-3, tol=1e-9)
