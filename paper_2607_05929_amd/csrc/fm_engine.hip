@@ -1114,8 +1114,13 @@ int finish_step(fm_plan* p, const Ctrl& c, int t, bool last, fm_outputs* out, fm
     int rc = set_outputs(p, out);
     if (rc) return rc;
   }
-  int rc = launch_commit(p);
-  if (rc) return rc;
+  // (nothing to commit for a solve without internal variables unless strain
+  // or stress fields are requested)
+  if (p->d.with_state || (last && out && (out->eps || out->sig))) {
+    const int rc = launch_commit(p);
+    if (rc) return rc;
+  }
+  int rc = 0;
   if (last && out && out->u) {
     hipLaunchKernelGGL(k_out_u, dim3(cdiv(p->g.Nn, 256)), dim3(256), 0, p->stream, p->self->S, 0);
     HIPCHK(hipGetLastError());
