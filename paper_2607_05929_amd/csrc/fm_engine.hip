@@ -719,7 +719,6 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
 // Persistent pipelined form of the strided E = 8 passes (FP32): at most
 // P_BLOCKS_PER_CU blocks per compute unit, a multiple of 8 blocks in all.
 constexpr int P_BLOCKS_PER_CU = 4;
-bool g_use_pipe = true;
 int g_num_cu = 0;
 
 // Resident blocks per compute unit of a kernel at a given dynamic LDS size
@@ -896,7 +895,7 @@ template <typename R, int MODE, int XP>
 void launch_w8_kind(int kind, int packed, dim3 grid, size_t lds, hipStream_t st, const PassDesc* P,
                     const int2* wl, const SolveDev* S) {
   if constexpr (!XP && sizeof(R) == 4) {
-    if (g_use_pipe && g_num_cu > 0) {
+    if (g_num_cu > 0) {
       launch_w8p_kind<MODE>(kind, packed, (int)grid.x, lds, st, P, wl, S);
       return;
     }
@@ -904,7 +903,7 @@ void launch_w8_kind(int kind, int packed, dim3 grid, size_t lds, hipStream_t st,
     // (the x inverse pass stays one tile per block: its u^f update reads
     // global memory after the transform, and those waits would take in the
     // prefetch; measured slower pipelined)
-    if (g_use_pipe && g_num_cu > 0 && packed) {
+    if (g_num_cu > 0 && packed) {
       launch_w8px_kind<MODE>(kind, (int)grid.x, lds, st, P, wl, S);
       return;
     }
