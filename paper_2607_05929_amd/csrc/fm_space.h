@@ -120,37 +120,53 @@ __device__ __forceinline__ void voxel_corners(const SolveDev& s, int x, int y, i
   }
 }
 
-// Strain at the integration points (HEX1: one point, all corners, weight
-// (2a_l - 1)/(4h); TETRA2: T1 on the even corners and T2 on the odd corners,
-// weight (2a_l - 1)/(2h)) from the corner values, the u* gradient at the
-// voxel centre and the tetrahedron cross-term correction.
-template <typename R>
-__device__ __forceinline__ void strain_from_corners(const SolveDev& s, const R (&u)[3][8], const R (&gs)[3][3],
-                                                    const R (&hc)[3][3], R eps[2][6]) {
-  const R f = (R)((s.scheme == 0) ? 0.25 / s.h : 0.5 / s.h);
+// Strain at the integration points of one scheme (SCH 0: HEX1, one point,
+// all corners; SCH 1: TETRA2, T1 on the even corners and T2 on the odd
+// corners) from the corner values, the u* gradient at the voxel centre and
+// the tetrahedron cross-term correction.  FP32 corner values are differences
+// to corner 0, which is exactly 0 and left out of the sums.
+template <typename R, int SCH>
+__device__ __forceinline__ void strain_points(const R (&u)[3][8], const R (&gs)[3][3], const R (&hc)[3][3], R f,
+                                              R eps[2][6]) {
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    if (r >= s.nppv) break;
+  for (int r = 0; r < (SCH == 1 ? 2 : 1); ++r) {
     R g[3][3];
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         R a = 0;
+        bool first = true;
 #pragma unroll
         for (int cidx = 0; cidx < 8; ++cidx) {
           const int bit[3] = {cidx & 1, (cidx >> 1) & 1, cidx >> 2};
           const int par = (bit[0] + bit[1] + bit[2]) & 1;
-          if (s.scheme == 1 && par != r) continue;
-          a += bit[l] ? u[q][cidx] : -u[q][cidx];
+          if (SCH == 1 && par != r) continue;
+          if (sizeof(R) == 4 && cidx == 0) continue;
+          const R t = bit[l] ? u[q][cidx] : -u[q][cidx];
+          a = first ? t : a + t;
+          first = false;
         }
-        g[l][q] = a * f + gs[l][q] + (r == 0 ? -hc[l][q] : hc[l][q]);
+        g[l][q] = a * f + gs[l][q];
+        if (SCH == 1) g[l][q] += r == 0 ? -hc[l][q] : hc[l][q];
       }
     eps[r][0] = g[0][0]; eps[r][1] = g[1][1]; eps[r][2] = g[2][2];
     eps[r][3] = (R)0.5 * (g[1][2] + g[2][1]);
     eps[r][4] = (R)0.5 * (g[0][2] + g[2][0]);
     eps[r][5] = (R)0.5 * (g[0][1] + g[1][0]);
   }
+}
+
+// Strain at the integration points (HEX1: weight (2a_l - 1)/(4h); TETRA2:
+// weight (2a_l - 1)/(2h)); the scheme is uniform over a solve, so the branch
+// is too.
+template <typename R>
+__device__ __forceinline__ void strain_from_corners(const SolveDev& s, const R (&u)[3][8], const R (&gs)[3][3],
+                                                    const R (&hc)[3][3], R eps[2][6]) {
+  if (s.scheme == 1)
+    strain_points<R, 1>(u, gs, hc, (R)(0.5 / s.h), eps);
+  else
+    strain_points<R, 0>(u, gs, hc, (R)(0.25 / s.h), eps);
 }
 
 // Strain at the integration points of voxel (x, y, z).
