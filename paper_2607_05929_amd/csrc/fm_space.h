@@ -499,18 +499,25 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const Solv
       const int64_t v = ((int64_t)vz * n1 + vy) * n0 + vx;
       const bool own = own_xy && zl >= Z0 && zl < n2;
       const bool zero_halo = zero_xy || (!s.wrap[2] && (zl < 0 || zl >= n2));
-      for (int r = 0; r < s.nppv; ++r) {
-        R sig[6];
-        if (from_buf) {
+      // the stresses of the voxel's points (one law branch per voxel, so the
+      // material entry is read once for both points)
+      R sig2[2][6];
+      if (from_buf) {
 #pragma unroll
-          for (int k = 0; k < 6; ++k) sig[k] = gconst((const R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v];
-        } else {
-          // solves without internal variables: elastic laws only
-          R st[7], stn[7];
+        for (int r = 0; r < 2; ++r)
+          if (r < s.nppv)
 #pragma unroll
-          for (int k = 0; k < 7; ++k) st[k] = 0;
-          law_elastic<R>(law, P, eps[r], sig, st, stn);
-        }
+            for (int k = 0; k < 6; ++k) sig2[r][k] = gconst((const R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v];
+      } else if (s.nppv == 2) {
+        // solves without internal variables: elastic laws only
+        law_elastic_pts<R, 2>(law, P, eps, sig2);
+      } else {
+        law_elastic_pts<R, 1>(law, P, eps, sig2);
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if (r >= s.nppv) break;
+        const R (&sig)[6] = sig2[r];
         // halo voxels across faces of axes periodic for no component hold zero
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
