@@ -30,6 +30,30 @@ __device__ __forceinline__ int vidx(int l, int q) {
   return l == q ? l : 6 - l - q;
 }
 
+// Per-thread sum of the block partials p[t * N + i] over the tiles
+// t = threadIdx.x + k blockDim.x, in increasing k.  Four tiles' loads are
+// issued before they are added (the same additions in the same order), so
+// a thread waits for one memory round trip per four tiles, not per tile.
+template <int N>
+__device__ __forceinline__ void sum_tiles(const double* __restrict__ p, int ntile, double (&a)[N]) {
+  const int b = blockDim.x;
+  int t = threadIdx.x;
+  for (; t + 3 * b < ntile; t += 4 * b) {
+    double v[4][N];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[u][i] = p[(int64_t)(t + u * b) * N + i];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] += v[u][i];
+  }
+  for (; t < ntile; t += b)
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] += p[(int64_t)t * N + i];
+}
+
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double* out) {
   __shared__ double red[4][N];
@@ -614,10 +638,8 @@ __global__ void __launch_bounds__(256) k_control(const SolveDev* __restrict__ S,
   const SolveDev& s = S[ids[blockIdx.x]];
   Ctrl* C = s.ctrl;
   if (C->status != ST_RUNNING) return;
-  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int t = threadIdx.x; t < s.ntile_s; t += blockDim.x)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) a[i] += s.part_s[(int64_t)t * NPART_S + i];
+  double a[NPART_S] = {0, 0, 0, 0, 0, 0, 0, 0};
+  sum_tiles<NPART_S>(s.part_s, s.ntile_s, a);
   __shared__ double tot[8];
   block_sum<8>(a, tot);
   __syncthreads();
@@ -719,9 +741,7 @@ __global__ void __launch_bounds__(256) k_alpha(const SolveDev* __restrict__ S, c
     double a[NGRAM];
 #pragma unroll
     for (int i = 0; i < NGRAM; ++i) a[i] = 0;
-    for (int t = threadIdx.x; t < s.ntile_d; t += blockDim.x)
-#pragma unroll
-      for (int i = 0; i < NGRAM; ++i) a[i] += s.part_g[(int64_t)t * NGRAM + i];
+    sum_tiles<NGRAM>(s.part_g, s.ntile_d, a);
     __shared__ double g[NGRAM];
     block_sum<NGRAM>(a, g);
     __syncthreads();
