@@ -143,8 +143,14 @@ typedef struct {
   int32_t step, iter;
   double  err;             /* equilibrium error before the update (FP64) */
   int32_t aa_applied;      /* Anderson combination used for this update */
-  int32_t pad_;
-  double  macro_sigma[6];
+  int32_t rs_fp64;         /* 1 if this iterate's strain, law and divergence ran in
+                              FP64 (an FP32-mixed plan moves them to FP64 once its
+                              error stalls within 100 tol, i.e. at the FP32 rounding
+                              floor; 0 for FP64 plans, which always compute in FP64) */
+  double  macro_sigma[6];  /* <sigma> of this iterate (FP64) */
+  double  t_us;            /* device time from the increment's first control
+                              evaluation to this one, microseconds (the
+                              difference of two entries is their iterations' time) */
 } fm_iter_entry;
 
 typedef struct {

@@ -50,7 +50,8 @@ class Outputs(C.Structure):
 
 class IterEntry(C.Structure):
     _fields_ = [("step", C.c_int32), ("iter", C.c_int32), ("err", C.c_double),
-                ("aa_applied", C.c_int32), ("pad_", C.c_int32), ("macro_sigma", C.c_double * 6)]
+                ("aa_applied", C.c_int32), ("rs_fp64", C.c_int32), ("macro_sigma", C.c_double * 6),
+                ("t_us", C.c_double)]
 
 
 class IterLog(C.Structure):
@@ -279,8 +280,9 @@ class Plan:
             res["sig"] = bufs["sig"].cpu().numpy().reshape(6, self.nppv, n3, n2, n1)
         if log is not None:
             res["log"] = [{"step": entries[i].step, "iter": entries[i].iter, "err": entries[i].err,
-                           "aa": bool(entries[i].aa_applied),
-                           "macro_sigma": list(entries[i].macro_sigma)} for i in range(log.count)]
+                           "aa": bool(entries[i].aa_applied), "rs_fp64": bool(entries[i].rs_fp64),
+                           "macro_sigma": list(entries[i].macro_sigma), "t_us": entries[i].t_us}
+                          for i in range(log.count)]
         return res
 
     def apply_green(self, x):

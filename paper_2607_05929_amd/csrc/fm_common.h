@@ -53,7 +53,8 @@ struct Ctrl {
   int32_t max_iter, depth, period;
   int32_t mixed_mask[6];
   int32_t best_m;         // iterate of the smallest error so far (this increment)
-  int32_t pad_[2];
+  int32_t fp32;           // the plan stores its fields in FP32 (FM_FP32_MIXED)
+  int32_t rs64;           // FP32 plan: real-space step (strain, law, divergence) now in FP64
   double alpha[MAX_DEPTH];
   double beta[MAX_DEPTH];
   double err, sumD2, sumS2;
@@ -89,6 +90,9 @@ struct LogEntry {
   double err;
   double aa;
   double macro[6];
+  uint64_t stamp;         // device wall clock at the control evaluation
+  int32_t rs64;           // real-space step of this iterate evaluated in FP64
+  int32_t pad_;
 };
 
 // Per-solve descriptor (device).

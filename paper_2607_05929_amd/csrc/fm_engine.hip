@@ -878,6 +878,12 @@ int set_lds_limits() {
                              (int)sdiv_lds_bytes(sizeof(R))));
   HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)sdiv_lds_bytes(sizeof(R))));
+  if constexpr (sizeof(R) == 4) {
+    HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 0, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sdiv_lds_bytes(8)));
+    HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 1, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sdiv_lds_bytes(8)));
+  }
   done = true;
   return 0;
 }
@@ -962,15 +968,21 @@ int launch_one(const Group& G, int k) {
   switch (k) {
     case 0:
       if (!G.nwl[7]) break;
+      // FP32 groups launch the FP32 and the FP64 real-space kernel; each
+      // solve's control block picks the one that works (the other returns)
       if (G.plastic) {
         // plastic solves: the law once per voxel (one thread each), then the
         // fused kernel reads those stresses
         if (G.nwl[0])
           hipLaunchKernelGGL((k_commit<R, 1, 1>), dim3(G.nwl[0] * (SPACE_TILE / 256)), dim3(256), 0, st, G.S, G.wl[0]);
         hipLaunchKernelGGL((k_sdiv<R, 1>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[7]);
-      }
-      else
+        if constexpr (sizeof(R) == 4)
+          hipLaunchKernelGGL((k_sdiv<R, 1, double>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(8), st, G.S, G.wl[7]);
+      } else {
         hipLaunchKernelGGL((k_sdiv<R, 0>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[7]);
+        if constexpr (sizeof(R) == 4)
+          hipLaunchKernelGGL((k_sdiv<R, 0, double>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(8), st, G.S, G.wl[7]);
+      }
       break;
     case 1: hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
     case 2: if (G.nwl[1]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]); break;
@@ -1055,6 +1067,20 @@ int launch_commit(fm_plan* p) {
   return p->d.prec == FM_FP64 ? launch_commit_t<double>(p) : launch_commit_t<float>(p);
 }
 
+// Tick rate of the device wall clock read by the control kernel (kHz).
+double wall_clock_khz() {
+  static double khz = -1;
+  if (khz < 0) {
+    int dev = 0, rate = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess)
+      khz = rate;
+    else
+      khz = 0;
+  }
+  return khz;
+}
+
 Ctrl* dev_ctrl(fm_plan* p) { return (Ctrl*)(p->ws + p->lay.ctrl); }
 LogEntry* dev_log(fm_plan* p) { return (LogEntry*)(p->ws + p->lay.log); }
 
@@ -1074,6 +1100,8 @@ int begin_step(fm_plan* p, const fm_load_step& st, int t, const Ctrl* prev) {
   c.tol = p->d.tol;
   c.lam0 = p->d.lambda0;
   c.mu0 = p->d.mu0;
+  c.fp32 = p->d.prec == FM_FP32_MIXED;
+  c.rs64 = 0;
   for (int q = 0; q < 3; ++q) {
     c.c[q] = st.c[q];
     for (int l = 0; l < 3; ++l) {
@@ -1137,10 +1165,12 @@ int finish_step(fm_plan* p, const Ctrl& c, int t, bool last, fm_outputs* out, fm
     std::vector<LogEntry> le(c.log_count);
     HIPCHK(hipMemcpyAsync(le.data(), dev_log(p), sizeof(LogEntry) * c.log_count, hipMemcpyDeviceToHost, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
+    const double khz = wall_clock_khz();
     for (int i = 0; i < c.log_count && log->count < log->capacity; ++i) {
       fm_iter_entry& e = log->entries[log->count++];
-      e.step = t; e.iter = i; e.err = le[i].err; e.aa_applied = le[i].aa != 0; e.pad_ = 0;
+      e.step = t; e.iter = i; e.err = le[i].err; e.aa_applied = le[i].aa != 0; e.rs_fp64 = le[i].rs64;
       for (int k = 0; k < 6; ++k) e.macro_sigma[k] = le[i].macro[k];
+      e.t_us = khz > 0 ? 1e3 * (double)(int64_t)(le[i].stamp - le[0].stamp) / khz : 0.0;
     }
   }
   return 0;

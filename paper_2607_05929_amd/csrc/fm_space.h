@@ -23,6 +23,8 @@
 namespace fm {
 
 constexpr int STALL_ITERS = 200;   // iterations without a 1 % better error (stagnation)
+constexpr int RS64_STALL = 8;      // same, for an FP32 plan to move its real-space step to FP64
+constexpr int RS64_WIN = 12;       // window of the convergence-rate test of that move
 constexpr int SPACE_TILE = 1024;   // voxels / nodes per 256-thread block (4 per thread)
 
 __device__ __forceinline__ int vidx(int l, int q) {
@@ -384,22 +386,22 @@ __device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, int J0, int J1) 
 // Divergence at the node of layer J2 (z factor fz per component: doubling on
 // a reflecting z face, 0 where not kept along z) from the column partials of
 // its four voxel columns; D written through Dn (this node in component 0).
-template <typename R>
-__device__ __forceinline__ void node_div(const R* __restrict__ P, int lx, int ly, const NodeXY<R>& nxy,
-                                         const R (&fz)[3], FM_GLOBAL R* Dn, int64_t Nn, R& accD) {
+template <typename CT, typename R>
+__device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int ly, const NodeXY<CT>& nxy,
+                                         const CT (&fz)[3], FM_GLOBAL R* Dn, int64_t Nn, CT& accD) {
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    R D = 0;
+    CT D = 0;
 #pragma unroll
     for (int b1 = 0; b1 < 2; ++b1)
 #pragma unroll
       for (int b0 = 0; b0 < 2; ++b0) {
-        const R t = P[(q * 4 + b1 * 2 + b0) * SD_VT + (ly + b1) * 32 + (lx + b0)];
-        D += ((nxy.drop >> (q * 4 + b1 * 2 + b0)) & 1) ? (R)0 : t;
+        const CT t = P[(q * 4 + b1 * 2 + b0) * SD_VT + (ly + b1) * 32 + (lx + b0)];
+        D += ((nxy.drop >> (q * 4 + b1 * 2 + b0)) & 1) ? (CT)0 : t;
       }
-    const R Dq = D * (nxy.fq[q] * fz[q]);
+    const CT Dq = D * (nxy.fq[q] * fz[q]);
     accD += Dq * Dq;
-    Dn[q * Nn] = Dq;
+    Dn[q * Nn] = (R)Dq;
   }
 }
 
@@ -408,15 +410,20 @@ __host__ __device__ inline size_t sdiv_lds_bytes(int rbytes) { return (size_t)12
 
 // PL = 1: the group holds solves with internal variables, whose stresses
 // come from the stress pass (k_commit with SIGMA = 1); the law evaluated here
-// is elastic.
-template <typename R, int PL>
-__global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
+// is elastic.  R is the storage type of the solve's fields (residual ring,
+// material table, stress buffer), CT the type the kernel computes in.  FP32
+// solves launch both the CT = float kernel and the CT = double one; the
+// control block's rs64 flag selects which of the two does the work (the
+// FP64 one once the FP32 residual has stalled at its rounding floor).
+template <typename R, int PL, typename CT = R>
+__global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4) k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
   const SolveDev& s = S[w.x];
   const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
   if (C->status != ST_RUNNING) return;
+  if (sizeof(R) == 4 && (C->rs64 != 0) != (sizeof(CT) == 8)) return;
   extern __shared__ __align__(16) char smem[];
-  R* sl = (R*)smem;                                    // column partials [12][SD_VT]
+  CT* sl = (CT*)smem;                                  // column partials [12][SD_VT]
   const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
   const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * s.sd_zc;
   const int Z1 = min(Z0 + s.sd_zc, s.N[2]);
@@ -429,14 +436,14 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const Solv
   const int J0 = X0 + lx, J1 = Y0 + ly;
   const bool has_node = lx < SD_TX && ly < SD_TY && J0 < s.N[0] && J1 < s.N[1];
   const FM_GLOBAL uint16_t* mat = gconst(s.mat);
-  const R wip = (R)1 / (R)s.nppv;
-  // per-thread partials in R (each thread sums at most 2 (sd_zc + 1) points),
+  const CT wip = (CT)1 / (CT)s.nppv;
+  // per-thread partials in CT (each thread sums at most 2 (sd_zc + 1) points),
   // FP64 across the block
-  R acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  CT acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // u* gradient of this voxel column: gA + gB z_c.  FP32: from the uniform
   // FP32 copies in the control block (gB and the cross terms stay scalar).
-  R gA[3][3], gB[3][3], hc[3][3];
-  if constexpr (sizeof(R) == 4) {
+  CT gA[3][3], gB[3][3], hc[3][3];
+  if constexpr (sizeof(CT) == 4) {
     // read before any store, so that the uniform values can live in scalars
     const float xc = (float)((vx + 0.5) * s.h), yc = (float)((vy + 0.5) * s.h);
 #pragma unroll
@@ -448,22 +455,22 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const Solv
         hc[l][q] = C->hc32[l * 3 + q];
       }
   } else {
-    ustar_grad_column<R>(s, C, vx, vy, gA, gB);
-    tet_cross_terms<R>(s, C, hc);
+    ustar_grad_column<CT>(s, C, vx, vy, gA, gB);
+    tet_cross_terms<CT>(s, C, hc);
   }
   // stresses of this column's voxel in the previous and current layer
   // ([point][Voigt], zero on halo voxels; HEX1 duplicates its point)
-  R sprev[2][6], scur[2][6];
+  CT sprev[2][6], scur[2][6];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k] = 0;
-  const NodeXY<R> nxy = node_xy<R>(s, J0, J1);
+  const NodeXY<CT> nxy = node_xy<CT>(s, J0, J1);
   // plastic solves read the stresses of the per-voxel stress pass
   const bool from_buf = PL && s.sig != nullptr;
   // FP32 corner carry: top corner 4 (FP64) and corners 5-7 minus it, per component
   double cu4[3] = {0, 0, 0};
-  R cdt[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  CT cdt[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   int vz_prev = -2;
   const int64_t N01 = (int64_t)s.N[0] * s.N[1];
   FM_GLOBAL R* Dcol = gmut((R*)s.Dring) + (int64_t)(C->m % s.depth) * 3 * s.Nn + (int64_t)J1 * s.N[0] + J0;
@@ -477,10 +484,10 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const Solv
       const int vz = map_vox(zl, n2, s.wrap[2]);
       const int law = gconst(s.mlaw)[mt_cur];
       const FM_GLOBAL R* P = gconst((const R*)s.mtab) + (int64_t)mt_cur * MT_STRIDE;
-      R eps[2][6];
+      CT eps[2][6];
       if (!from_buf) {
-        R u[3][8], gs[3][3];
-        if constexpr (sizeof(R) == 4) {
+        CT u[3][8], gs[3][3];
+        if constexpr (sizeof(CT) == 4) {
           // FP32: FP64 differences to corner 0, with the bottom face taken
           // from the previous layer's top face when the layers are adjacent
           // (same nodes, same differences: bitwise the full computation)
@@ -497,35 +504,35 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const Solv
             } else {
               u0 = uq[0];
 #pragma unroll
-              for (int c = 1; c < 4; ++c) u[q][c] = (R)(uq[(c & 1) + (c >> 1) * s.N[0]] - u0);
+              for (int c = 1; c < 4; ++c) u[q][c] = (CT)(uq[(c & 1) + (c >> 1) * s.N[0]] - u0);
             }
             u[q][0] = 0;
             double top[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) top[c] = uq[(c & 1) + (c >> 1) * s.N[0] + N01];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) u[q][4 + c] = (R)(top[c] - u0);
+            for (int c = 0; c < 4; ++c) u[q][4 + c] = (CT)(top[c] - u0);
             cu4[q] = top[0];
 #pragma unroll
-            for (int c = 1; c < 4; ++c) cdt[q][c - 1] = (R)(top[c] - top[0]);
+            for (int c = 1; c < 4; ++c) cdt[q][c - 1] = (CT)(top[c] - top[0]);
           }
           vz_prev = vz;
         } else {
-          voxel_corners<R>(s, vx, vy, vz, u);
+          voxel_corners<CT>(s, vx, vy, vz, u);
         }
-        const R zc = (R)((vz + 0.5) * s.h);
+        const CT zc = (CT)((vz + 0.5) * s.h);
 #pragma unroll
         for (int l = 0; l < 3; ++l)
 #pragma unroll
           for (int q = 0; q < 3; ++q) gs[l][q] = gA[l][q] + gB[l][q] * zc;
-        strain_from_corners<R>(s, u, gs, hc, eps);
+        strain_from_corners<CT>(s, u, gs, hc, eps);
       }
       const int64_t v = ((int64_t)vz * n1 + vy) * n0 + vx;
       const bool own = own_xy && zl >= Z0 && zl < n2;
       const bool zero_halo = zero_xy || (!s.wrap[2] && (zl < 0 || zl >= n2));
       // the stresses of the voxel's points (one law branch per voxel, so the
       // material entry is read once for both points)
-      R sig2[2][6];
+      CT sig2[2][6];
       if (from_buf) {
 #pragma unroll
         for (int r = 0; r < 2; ++r)
@@ -534,26 +541,26 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const Solv
             for (int k = 0; k < 6; ++k) sig2[r][k] = gconst((const R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v];
       } else if (s.nppv == 2) {
         // solves without internal variables: elastic laws only
-        law_elastic_pts<R, 2>(law, P, eps, sig2);
+        law_elastic_pts<CT, 2>(law, P, eps, sig2);
       } else {
-        law_elastic_pts<R, 1>(law, P, eps, sig2);
+        law_elastic_pts<CT, 1>(law, P, eps, sig2);
       }
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         if (r >= s.nppv) break;
-        const R (&sig)[6] = sig2[r];
+        const CT (&sig)[6] = sig2[r];
         // halo voxels across faces of axes periodic for no component hold zero
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          const R val = zero_halo ? (R)0 : sig[k];
+          const CT val = zero_halo ? (CT)0 : sig[k];
           scur[0][k] = r == 0 ? val : scur[0][k];
           scur[1][k] = r == 0 ? val : (r == 1 ? val : scur[1][k]);
         }
         if (own) {
-          R n2s = 0;
+          CT n2s = 0;
 #pragma unroll
           for (int k = 0; k < 6; ++k) {
-            n2s += (k < 3 ? (R)1 : (R)2) * sig[k] * sig[k];
+            n2s += (k < 3 ? (CT)1 : (CT)2) * sig[k] * sig[k];
             acc[1 + k] += wip * sig[k];
           }
           acc[0] += wip * n2s;
@@ -561,15 +568,15 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 1 : 4) k_sdiv(const Solv
       }
     }
     if (zl >= Z0) {
-      column_partials<R>(s, sprev, scur, zl, sl + threadIdx.x);
-      R fz[3];
+      column_partials<CT>(s, sprev, scur, zl, sl + threadIdx.x);
+      CT fz[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const bool face = s.kinds[q][2] != K_DFT && (zl == 0 || zl == n2);
-        fz[q] = node_kept(s.kinds[q][2], n2, zl) ? (face ? (R)2 : (R)1) : (R)0;
+        fz[q] = node_kept(s.kinds[q][2], n2, zl) ? (face ? (CT)2 : (CT)1) : (CT)0;
       }
       __syncthreads();
-      if (has_node) node_div<R>(sl, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7]);
+      if (has_node) node_div<CT, R>(sl, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7]);
       __syncthreads();
     }
 #pragma unroll
@@ -671,18 +678,41 @@ __global__ void __launch_bounds__(256) k_control(const SolveDev* __restrict__ S,
     LogEntry& e = s.log[m];
     e.err = err; e.aa = 0;
     for (int i = 0; i < 6; ++i) e.macro[i] = C->macro[i];
+    e.stamp = wall_clock64();
+    e.rs64 = C->rs64;
     C->log_count = m + 1;
   }
   if (err < C->tol && mixed_ok) { C->status = ST_CONVERGED; return; }
   if (m >= C->max_iter) { C->status = ST_MAXITER; return; }
-  // Stagnation: an error that has not fallen below 0.99 of its best for
-  // STALL_ITERS iterations while within 100 tol sits at the rounding floor of
-  // the precision (FP32 on slowly converging problems); the increment stops
-  // there, reported as not converged, instead of running to max_iter.
+  // Rounding floor of the FP32 real-space step.  Within 100 tol, an FP32
+  // plan whose error falls, over the last RS64_WIN iterations, at less than
+  // half its average rate since the start of the increment (or not at all
+  // for RS64_STALL iterations) is slowed by the rounding of its FP32 strain,
+  // stress and divergence: from the next iterate on the real-space step runs
+  // in FP64.  The transforms, the Green operator and the Anderson update
+  // only precondition the fixed point, so they stay FP32.  An error that
+  // still stalls for STALL_ITERS iterations sits at the floor of the
+  // precision; the increment stops there, reported as not converged,
+  // instead of running to max_iter.
+  bool better = false;
   if (err < 0.99 * C->best_err) {
     C->best_err = err;
     C->best_m = m;
-  } else if (m - C->best_m >= STALL_ITERS && err < 100.0 * C->tol) {
+    better = true;
+  }
+  if (C->fp32 && !C->rs64 && err < 100.0 * C->tol && err > 0) {
+    bool slow = !better && m - C->best_m >= RS64_STALL;
+    if (m >= 2 * RS64_WIN && m <= C->max_iter) {
+      const double e0 = s.log[0].err, ew = s.log[m - RS64_WIN].err;
+      if (e0 > err && e0 < INFINITY && ew > 0 && ew < INFINITY)
+        slow = slow || log(ew / err) / RS64_WIN < 0.5 * log(e0 / err) / m;
+    }
+    if (slow) {
+      C->rs64 = 1;
+      C->best_err = err;
+      C->best_m = m;
+    }
+  } else if (!better && m - C->best_m >= STALL_ITERS && err < 100.0 * C->tol) {
     C->status = ST_MAXITER;
     return;
   }

@@ -62,10 +62,43 @@ def test_workspace_bytes_and_validation(lib):
     assert lib.fm_workspace_bytes(C.byref(bad3)) == 0
 
 
+def _c_layout(structs):
+    """Field offsets and sizes of header structs, from a C program compiled
+    against include/fmsolve.h with the host compiler."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fmsolve.h"', "int main(void) {"]
+    for cname, fields in structs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        with open(src, "w") as f:
+            f.write("\n".join(lines))
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), "-o", exe, src], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    res = {}
+    for ln in out.splitlines():
+        cname, field, val = ln.split()
+        res[(cname, field)] = int(val)
+    return res
+
+
 def test_struct_layouts_match_header():
-    from paper_2607_05929_amd import binding
-    # sizes implied by the header's field order on LP64
-    assert C.sizeof(binding.PlanDesc) == 4 * 3 + 4 + 8 + 4 * 18 + 4 * 2 + 8 * 2 + 4 + 4 + 8 + 4 * 5 + 4
-    assert C.sizeof(binding.Material) == 8 + 8 * 8 + 8 * 4
-    assert C.sizeof(binding.LoadStep) == 8 * (3 + 9 + 27) + 4 * 6 + 8 * 6 + 8
-    assert C.sizeof(binding.IterEntry) == 4 * 2 + 8 + 4 * 2 + 8 * 6
+    """Every ctypes mirror in the binding has the header's field offsets and size."""
+    from paper_2607_05929_amd import binding as B
+    pairs = [("fm_plan_desc", B.PlanDesc), ("fm_material", B.Material), ("fm_load_step", B.LoadStep),
+             ("fm_outputs", B.Outputs), ("fm_iter_entry", B.IterEntry), ("fm_iter_log", B.IterLog),
+             ("fm_request", B.Request), ("fm_stats", B.Stats)]
+    lay = _c_layout([(c, [f for f, _ in py._fields_]) for c, py in pairs])
+    for cname, py in pairs:
+        assert lay[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert lay[(cname, f)] == getattr(py, f).offset, (cname, f)
