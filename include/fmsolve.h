@@ -116,7 +116,11 @@ typedef struct {
  * at node positions x = (i h, j h, k h).  mixed_mask[c] != 0 makes Voigt
  * component c of sym(G) stress-controlled: it is moved after every iteration
  * so that <sigma>_c reaches mixed_target[c] (Sec. 3.2 normal-mixed loading).
- * Applied tractions are zero (Neumann faces are traction-free). */
+ * traction[i][a][q] is the applied traction T*_q, uniform over face a of axis
+ * i (Sec. 2.2: sigma_iq (-1)^(a+1) = T*_q, i.e. the traction vector
+ * sigma n); it may be non-zero only where u_q is Neumann on that face
+ * (FM_E_BC otherwise).  The solver adds D* = div_d P*, the divergence of the
+ * applied stress that is 2 T* on the face's mirror voxels (Fig. NeumannBC). */
 typedef struct {
   double  c[3];
   double  G[3][3];
@@ -124,6 +128,7 @@ typedef struct {
   int32_t mixed_mask[6];
   double  mixed_target[6];
   double  dt;
+  double  traction[3][2][3];
 } fm_load_step;
 
 /* Outputs; every pointer may be NULL.  u, eps, sig are device pointers
@@ -207,7 +212,7 @@ int fm_batch_solve(fm_plan* const* plans, int32_t n_plans,
  * fm_apply_green: d_w = IDT( DT(d_x) / den ) per component, i.e. minus the
  * B0 / 2mu0 discrete Green operator (Eqs. NSGO2_*, NSGO1_*) applied to the
  * node field d_x, with the transforms of Table 1 and the dismissed points of
- * Sec. 3.2 (d_x and d_w: device FP64, 3 x nodes).  Overwrites the plan's
+ * Sec. 2.7.2 (d_x and d_w: device FP64, 3 x nodes).  Overwrites the plan's
  * displacement and history (call fm_set_material again before fm_solve).
  *
  * fm_residual: for the fluctuation d_uf (device FP64, 3 x nodes) and the

@@ -172,7 +172,7 @@ def forward_1d(g: np.ndarray, kind: int, axis: int) -> np.ndarray:
 def inverse_1d(G: np.ndarray, kind: int, axis: int, n: int) -> np.ndarray:
     """Inverse of ``forward_1d``; returns all n+1 node values with the
     dismissed points filled (anti-symmetric face nodes = 0, periodic node n =
-    node 0) as in Sec. 3.2 (Domain decomposition and discrete transformations)."""
+    node 0) as in Sec. 2.7.2 (Domain decomposition and discrete transformations)."""
     G = np.moveaxis(np.asarray(G), axis, -1)
     shape = G.shape[:-1] + (n + 1,)
     dtype = np.result_type(G.dtype, np.float64)

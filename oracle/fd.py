@@ -171,3 +171,38 @@ def kept_mask(exts, n) -> np.ndarray:
         shape = [1, 1, 1]; shape[i] = n[i] + 1
         m &= keep.reshape(shape)
     return m
+
+
+def applied_divergence(T: np.ndarray, ext3, scheme: int, h: float, n) -> np.ndarray:
+    """D* = div_d P* of the applied stress of non-vanishing Neumann conditions
+    (Sec. 2.2, Fig. NeumannBC): P* vanishes at every voxel of the grid; on the
+    mirror voxels across a face S_{i a} where u_q is Neumann, its entry P*_iq
+    is twice the face value that the traction prescribes, P_iq (-1)^(a+1) =
+    T*_q, so that P* interpolated to the face equals it.  T[i, a, q] is
+    uniform over the face, so the whole mirror layer (edges and corners of
+    the padded grid included) carries the same value.  The stencils are those
+    of the divergence; dismissed nodes are 0."""
+    n1, n2, n3 = n
+    out = np.zeros((3, n1 + 1, n2 + 1, n3 + 1))
+    for q in range(3):
+        acc = np.zeros((n1 + 1, n2 + 1, n3 + 1))
+        for i in range(3):
+            if not np.any(T[i, :, q]):
+                continue
+            A = np.zeros((n1 + 2, n2 + 2, n3 + 2))
+            for a in (0, 1):
+                if T[i, a, q] == 0:
+                    continue
+                if ext3[q][i][a] != _dt.EXT_S:
+                    raise ValueError("a traction needs a Neumann condition of that component on that face")
+                sl = [slice(None)] * 3
+                sl[i] = 0 if a == 0 else -1
+                A[tuple(sl)] = 2.0 * (-1.0) ** (a + 1) * T[i, a, q]
+            if scheme == 0:
+                acc += cell_derivs(A, 0, h)[i]
+            else:
+                d = cell_derivs(A, 1, h)
+                acc += 0.5 * (d[1, i] + d[0, i])
+        out[q] = acc
+        zero_dismissed(out[q], ext3[q])
+    return out

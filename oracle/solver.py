@@ -1,7 +1,8 @@
 """Algorithm 1 (algFFT) of the paper, written out step by step in FP64.
 
 For every load increment (the set-up steps of Algorithm 1): update u* and
-its discrete gradient (D* = 0, no applied tractions) and predict u^f from the
+its discrete gradient, the divergence D* of the applied stress of the
+Neumann faces that carry a traction (Sec. 2.2), and predict u^f from the
 previous increment; then iterate (the loop of Algorithm 1):
 
   * strain at the integration points, grad_d u = grad_d u^f + grad_d u*
@@ -16,7 +17,8 @@ previous increment; then iterate (the loop of Algorithm 1):
 Readings where the paper is silent or garbled (listed in the design doc):
   * error  = h sqrt( sum_kept |D|^2 / sum_ip w_ip |sigma|_F^2 ), w_ip = 1/n_ppv
     (squared L2 norms; the printed ratio of norms is not dimensionless);
-  * Anderson (Sec. 2.3: "every 2 or 3 iterations ... previous 4 couples"):
+  * Anderson (Sec. 2.3 applies it every second or third iteration with a
+    history of four pairs, without further detail):
     type-II Anderson on the Green input x with g_m = p_m, f_m = g_m - x_{m-1},
     the last ``aa_depth`` pairs, applied when m >= 2 and m % aa_period == 0,
     weights minimising |sum a_j f_j|^2 with sum a_j = 1 (normal equations,
@@ -77,6 +79,13 @@ class Plan:
     def div(self, S):
         return _fd.divergence(S, self.exts, self.scheme, self.h)
 
+    def div_applied(self, T):
+        """D* = div_d P* for the face tractions T[axis, face, component] (0 when none)."""
+        T = np.asarray(T, dtype=np.float64)
+        if not np.any(T):
+            return 0.0
+        return _fd.applied_divergence(T, self.exts, self.scheme, self.h, self.n)
+
     def L0(self, u):
         """div_d(R0 : grad_d u) with R0 = B0 (2 mu0 grad u + lambda0 grad u . I)."""
         g = self.grad(u)
@@ -96,6 +105,18 @@ class Plan:
 
     def dot_kept(self, a, b):
         return float(sum(np.sum(a[q][self.kept[q]] * b[q][self.kept[q]]) for q in range(3)))
+
+
+def equilibrium_error(pl: Plan, D: np.ndarray, sig: np.ndarray) -> float:
+    """Eq. equilibrium_condition read with squared L2 norms (the printed ratio
+    of norms is not dimensionless): h sqrt(sum over each component's kept
+    nodes of D^2 / sum over the integration points of w_ip |sigma|_F^2), with
+    w_ip = 1 / n_ppv.  A stress-free body has error 0 if D vanishes, else inf."""
+    sD = pl.dot_kept(D, D)
+    sS = float(np.sum(sig * sig)) / pl.nppv
+    if sS > 0:
+        return pl.h * np.sqrt(sD / sS)
+    return 0.0 if sD == 0 else np.inf
 
 
 def anderson_weights(F: np.ndarray):
@@ -144,6 +165,7 @@ def solve(prob, callback=None):
                 G[i, j] = Gprev[i, j]
                 G[j, i] = Gprev[j, i]
         S_idx = np.nonzero(step.mixed_mask)[0]
+        Dstar = pl.div_applied(getattr(step, "traction", np.zeros((3, 2, 3))))
         hist = []
         x_prev = pl.L0(uf)
         converged = False
@@ -153,13 +175,8 @@ def solve(prob, callback=None):
             gu = pl.grad(uf) + pl.grad(us)
             eps = 0.5 * (gu + np.swapaxes(gu, -1, -2))
             sig, trial = mats.stress(eps, state, step.dt)
-            Dv = pl.div(sig)
-            sD = pl.dot_kept(Dv, Dv)
-            sS = float(np.sum(sig * sig)) / pl.nppv
-            if sS > 0:
-                err = pl.h * np.sqrt(sD / sS)
-            else:
-                err = 0.0 if sD == 0 else np.inf
+            Dv = pl.div(sig) + Dstar
+            err = equilibrium_error(pl, Dv, sig)
             ms = sig.mean(axis=(0, 1, 2, 3))
             mvo = np.array([ms[i, j] for (i, j) in VOIGT])
             mixed_ok = True

@@ -39,7 +39,7 @@ class Material(C.Structure):
 class LoadStep(C.Structure):
     _fields_ = [("c", C.c_double * 3), ("G", C.c_double * 9), ("H", C.c_double * 27),
                 ("mixed_mask", C.c_int32 * 6), ("mixed_target", C.c_double * 6),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("traction", C.c_double * 18)]
 
 
 class Outputs(C.Structure):
@@ -196,6 +196,9 @@ def load_steps(steps):
             e.mixed_mask[i] = int(s.mixed_mask[i])
             e.mixed_target[i] = float(s.mixed_target[i])
         e.dt = float(s.dt)
+        T = np.asarray(getattr(s, "traction", np.zeros((3, 2, 3))), dtype=np.float64).reshape(-1)
+        for i in range(18):
+            e.traction[i] = T[i]
     return arr
 
 

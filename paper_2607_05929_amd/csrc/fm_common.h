@@ -71,7 +71,10 @@ struct Ctrl {
   float g32[9];
   float h32[27];
   float hc32[9];
-  int32_t pad2_;
+  int32_t has_trac;       // some face carries an applied traction
+  // D* of the applied tractions: 2 T_q / h per [axis][face][component]
+  double dstar[18];
+  float dstar32[18];
 };
 
 // Refresh the FP32 copies of G, H and the TETRA2 cross terms (h_half = h/2

@@ -1084,8 +1084,23 @@ double wall_clock_khz() {
 Ctrl* dev_ctrl(fm_plan* p) { return (Ctrl*)(p->ws + p->lay.ctrl); }
 LogEntry* dev_log(fm_plan* p) { return (LogEntry*)(p->ws + p->lay.log); }
 
+// Applied tractions only on Neumann faces of their component (Sec. 2.2).
+int check_tractions(const fm_plan_desc& d, const fm_load_step* steps, int n) {
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < 3; ++i)
+      for (int a = 0; a < 2; ++a)
+        for (int q = 0; q < 3; ++q) {
+          const double T = steps[k].traction[i][a][q];
+          if (!std::isfinite(T)) return fail(FM_E_INVALID_ARG, "traction is not finite");
+          if (T != 0 && d.bc[q][i][a] != FM_BC_NEUMANN)
+            return fail(FM_E_BC, "a traction needs a Neumann condition of that component on that face");
+        }
+  return 0;
+}
+
 // Start increment `t` of a plan: upload the control block.
 int begin_step(fm_plan* p, const fm_load_step& st, int t, const Ctrl* prev) {
+  if (int rc = check_tractions(p->d, &st, 1)) return rc;
   Ctrl c;
   std::memset(&c, 0, sizeof(c));
   c.m = 0;
@@ -1102,6 +1117,15 @@ int begin_step(fm_plan* p, const fm_load_step& st, int t, const Ctrl* prev) {
   c.mu0 = p->d.mu0;
   c.fp32 = p->d.prec == FM_FP32_MIXED;
   c.rs64 = 0;
+  c.has_trac = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 2; ++a)
+      for (int q = 0; q < 3; ++q) {
+        const double d = 2.0 * st.traction[i][a][q] / p->d.h;
+        c.dstar[(i * 2 + a) * 3 + q] = d;
+        c.dstar32[(i * 2 + a) * 3 + q] = (float)d;
+        c.has_trac |= d != 0;
+      }
   for (int q = 0; q < 3; ++q) {
     c.c[q] = st.c[q];
     for (int l = 0; l < 3; ++l) {
@@ -1376,6 +1400,7 @@ int fm_set_material(fm_plan* p, const int32_t* d_mat_id, int32_t n_mat, const fm
 int fm_solve(fm_plan* p, const fm_load_step* steps, int32_t n_steps, fm_outputs* out, fm_iter_log* log) {
   if (!p || !steps || n_steps < 1) return fail(FM_E_INVALID_ARG, "null plan or empty load path");
   if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called before fm_solve");
+  if (int rc = check_tractions(p->d, steps, n_steps)) return rc;
   if (log) log->count = 0;
   p->total_iters = 0;
   int result = FM_OK;

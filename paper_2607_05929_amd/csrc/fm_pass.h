@@ -1,4 +1,4 @@
-// Axis passes of the 3D discrete transforms (Sec. 2.4, Sec. 3.2 "Domain
+// Axis passes of the 3D discrete transforms (Sec. 2.4, Sec. 2.7.2 "Domain
 // decomposition and discrete transformations"), one kernel launch per pass
 // covering every (solve, component) of a batch through a work list.
 //

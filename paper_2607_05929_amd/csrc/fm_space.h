@@ -353,13 +353,37 @@ __device__ __forceinline__ void column_partials(const SolveDev& s, const R (&sp)
 template <typename R>
 struct NodeXY {
   R fq[3];
+  R tq[3];      // D* of the applied tractions of the x and y faces the node lies on
   int drop;
 };
 
+// D* of a uniform traction T on a Neumann face of u_q (Sec. 2.2): the
+// applied stress P* is twice the face value on the face's mirror voxels and
+// zero in the grid, so at every kept node of that face the stencil sums four
+// mirror voxels of weight 1/(4h) (HEX1; TETRA2 gives the same total), with
+// signs that make D*_q = 2 T_q / h on both faces of an axis.  The control
+// block holds 2 T / h per [axis][face][component].
 template <typename R>
-__device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, int J0, int J1) {
+__device__ __forceinline__ R dstar(const FM_GLOBAL Ctrl* C, int i, int a, int q) {
+  if constexpr (sizeof(R) == 4) return C->dstar32[(i * 2 + a) * 3 + q];
+  else return (R)C->dstar[(i * 2 + a) * 3 + q];
+}
+
+template <typename R>
+__device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, const FM_GLOBAL Ctrl* C, int J0, int J1) {
   NodeXY<R> r;
   r.drop = 0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    R t = 0;
+    if (C->has_trac) {
+      if (J0 == 0) t += dstar<R>(C, 0, 0, q);
+      if (J0 == s.n[0]) t += dstar<R>(C, 0, 1, q);
+      if (J1 == 0) t += dstar<R>(C, 1, 0, q);
+      if (J1 == s.n[1]) t += dstar<R>(C, 1, 1, q);
+    }
+    r.tq[q] = t;
+  }
   const int J[2] = {J0, J1};
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -388,7 +412,8 @@ __device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, int J0, int J1) 
 // its four voxel columns; D written through Dn (this node in component 0).
 template <typename CT, typename R>
 __device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int ly, const NodeXY<CT>& nxy,
-                                         const CT (&fz)[3], FM_GLOBAL R* Dn, int64_t Nn, CT& accD) {
+                                         const CT (&fz)[3], const CT (&tz)[3], FM_GLOBAL R* Dn, int64_t Nn,
+                                         CT& accD) {
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     CT D = 0;
@@ -399,7 +424,8 @@ __device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int l
         const CT t = P[(q * 4 + b1 * 2 + b0) * SD_VT + (ly + b1) * 32 + (lx + b0)];
         D += ((nxy.drop >> (q * 4 + b1 * 2 + b0)) & 1) ? (CT)0 : t;
       }
-    const CT Dq = D * (nxy.fq[q] * fz[q]);
+    const CT f = nxy.fq[q] * fz[q];
+    const CT Dq = D * f + (f != (CT)0 ? nxy.tq[q] + tz[q] : (CT)0);
     accD += Dq * Dq;
     Dn[q * Nn] = (R)Dq;
   }
@@ -465,7 +491,7 @@ __global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4) k_sdiv(const Sol
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k] = 0;
-  const NodeXY<CT> nxy = node_xy<CT>(s, J0, J1);
+  const NodeXY<CT> nxy = node_xy<CT>(s, C, J0, J1);
   // plastic solves read the stresses of the per-voxel stress pass
   const bool from_buf = PL && s.sig != nullptr;
   // FP32 corner carry: top corner 4 (FP64) and corners 5-7 minus it, per component
@@ -569,14 +595,15 @@ __global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4) k_sdiv(const Sol
     }
     if (zl >= Z0) {
       column_partials<CT>(s, sprev, scur, zl, sl + threadIdx.x);
-      CT fz[3];
+      CT fz[3], tz[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const bool face = s.kinds[q][2] != K_DFT && (zl == 0 || zl == n2);
         fz[q] = node_kept(s.kinds[q][2], n2, zl) ? (face ? (CT)2 : (CT)1) : (CT)0;
+        tz[q] = !C->has_trac ? (CT)0 : zl == 0 ? dstar<CT>(C, 2, 0, q) : zl == n2 ? dstar<CT>(C, 2, 1, q) : (CT)0;
       }
       __syncthreads();
-      if (has_node) node_div<CT, R>(sl, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7]);
+      if (has_node) node_div<CT, R>(sl, lx, ly, nxy, fz, tz, Dcol + (int64_t)zl * N01, s.Nn, acc[7]);
       __syncthreads();
     }
 #pragma unroll

@@ -137,7 +137,7 @@ def test_cp_fp32(B):
     e = rel_err(got["macro_sigma"], ref["macro_sigma"])
     print(f"cp fp32 iters {got['iters']} macro err {e:.2e}", flush=True)
     assert all(got["converged"])
-    assert e < 1e-4
+    assert e < 1e-5
 
 
 def _batch_problems():

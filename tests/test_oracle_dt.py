@@ -2,7 +2,7 @@
 
 P1: DT(G) = alpha^-1 DFT(E)[mapped k] on the explicitly built extension E.
 P2: the O(n^2) sums written out from Table 1 equal the scipy-based transforms.
-P3: round trip iDT(DT(G)) = G on the kept nodes (Sec. 3.2 validation recipe).
+P3: round trip iDT(DT(G)) = G on the kept nodes (Sec. 2.7.2 validation recipe).
 """
 import numpy as np
 import pytest

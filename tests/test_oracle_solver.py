@@ -213,3 +213,24 @@ def test_mixed_control_uniaxial_stress_j2():
         exact = E * e if e <= ey else sy0 + Et * (e - ey)
         assert r["macro_sigma"][t][2] == pytest.approx(exact, rel=1e-8)
         assert abs(r["macro_sigma"][t][0]) < 1e-10 * exact
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+def test_cantilever_beam_theory(scheme):
+    """P14 (approximate): the cantilever under a uniform load on its top face
+    (Sec. 3.1.1, Eq. analytical_sol_bending_elastic_own_weight) deflects as
+    beam theory predicts to within the shear-deformation and discretisation
+    gap of a coarse 40 x 4 x 4 grid (about 7 % HEX1, 2 % TETRA2)."""
+    n = (40, 4, 4)
+    prob = W.cantilever(n=n, t2=1e-3, scheme=scheme, tol=1e-8)
+    r = solver.solve(prob)
+    assert r["converged"][0]
+    lam, mu = 120.0, 80.0
+    E = mu * (3 * lam + 2 * mu) / (lam + mu)
+    I = n[2] * n[1] ** 3 / 12.0
+    L = n[0]
+    tip = -1e-3 * n[2] * L ** 4 / (8.0 * E * I)
+    uy = r["u"][1][n[2] // 2, n[1] // 2, -1]
+    assert 0.97 < uy / tip < 1.10
+    # the load is carried: the clamped face reacts the applied force
+    assert r["macro_sigma"][0][5] != 0.0

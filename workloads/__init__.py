@@ -89,10 +89,14 @@ class LoadStep:
     mixed_mask: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(6, dtype=np.int32))
     mixed_target: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(6))
     dt: float = 1.0
+    # applied traction T*[axis i][face a][component q], uniform over the face
+    # S_{i a}; non-zero only where u_q is Neumann on that face
+    traction: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((3, 2, 3)))
 
     def copy(self) -> "LoadStep":
         return LoadStep(self.c.copy(), self.G.copy(), self.H.copy(),
-                        self.mixed_mask.copy(), self.mixed_target.copy(), self.dt)
+                        self.mixed_mask.copy(), self.mixed_target.copy(), self.dt,
+                        self.traction.copy())
 
 
 def step_affine(G) -> LoadStep:
@@ -393,6 +397,24 @@ def cp_polycrystal(rng, nv, n_grains, prec=FP32_MIXED, n_steps=10, eps_max=5e-3,
     return Problem(n=n, h=1.0, bc=bc, scheme=scheme, green=GREEN_B0, lambda0=lam0,
                    mu0=mu0, materials=mats, mat_id=ids, steps=steps, tol=tol,
                    max_iter=3000, prec=prec, name=f"cp{nv}")
+
+
+def cantilever(n=(100, 10, 10), h=1.0, t2=1e-3, scheme=HEX1, n_steps=1, prec=FP64, tol=1e-8) -> Problem:
+    """Elastic cantilever (lambda 120, mu 80 GPa) clamped on the face x = 0
+    (every component Dirichlet, u* = 0) and loaded on the top face y = n_y h
+    by a uniform traction -t2 e_y; every other face is traction-free.  The
+    increments scale the load linearly up to t2."""
+    bc = np.full((3, 3, 2), N, dtype=np.int32)
+    bc[:, 0, 0] = D
+    steps = []
+    for k in range(1, n_steps + 1):
+        s = LoadStep()
+        s.traction[1, 1, 1] = -t2 * k / n_steps
+        steps.append(s)
+    lam, mu = 120.0, 80.0
+    return Problem(n=tuple(n), h=h, bc=bc, scheme=scheme, green=GREEN_B0, lambda0=lam, mu0=mu,
+                   materials=[mat_iso(lam, mu)], mat_id=np.zeros((n[2], n[1], n[0]), dtype=np.int32),
+                   steps=steps, tol=tol, max_iter=20000, prec=prec, name="cantilever")
 
 
 @dataclasses.dataclass
