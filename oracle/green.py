@@ -93,3 +93,109 @@ def apply(p_hat: np.ndarray, kinds, n, q, scheme, h, lam0, mu0, green) -> np.nda
     ok = ~mask
     out[ok] = -p_hat[ok] / den[ok]
     return out
+
+
+# ---------------------------------------------------------------------------
+# C0 discrete Green operator (Sec. 2.6.1, small-strain form of Appendix A)
+# ---------------------------------------------------------------------------
+OPPOSITE = {_dt.DFT: _dt.DFT, _dt.DCT1: _dt.DST1, _dt.DST1: _dt.DCT1,
+            _dt.DCT3: _dt.DST3, _dt.DST3: _dt.DCT3}
+
+
+def c0_compatible(kinds) -> bool:
+    """Eq. SGO_BCs ("normal-mixed" conditions): along every axis a, the
+    extension of the normal component u_a is the opposite of that of the two
+    tangential components (periodic stays periodic), so that p and u^f share
+    one extension.  ``kinds[q][a]`` is the Table 1 transform of u_q along a."""
+    for a in range(3):
+        for q in range(3):
+            if q != a and kinds[q][a] != OPPOSITE[kinds[a][a]]:
+                return False
+    return True
+
+
+def _extension_map(kind: int, n: int):
+    """Index into the n+1 node values and sign of every position of the
+    virtually extended periodic field (Table 1, Fig. Symmetries); sign 0 where
+    the extension is forced to zero."""
+    probe = np.arange(1, n + 2, dtype=np.float64)
+    e = _dt.extension(probe, kind).real
+    idx = np.where(e == 0, 0, np.abs(e).astype(np.int64) - 1)
+    return idx, np.sign(e)
+
+
+def _extend3(g, kinds, n):
+    maps = [_extension_map(kinds[a], n[a]) for a in range(3)]
+    E = g[np.ix_(maps[0][0], maps[1][0], maps[2][0])]
+    return E * maps[0][1][:, None, None] * maps[1][1][None, :, None] * maps[2][1][None, None, :]
+
+
+def c0_apply(p, kinds, n, scheme: int, h: float, lam0: float, mu0: float) -> np.ndarray:
+    """u^f = DGO(p) of the C0 reference medium (small strain, Appendix A) on
+    the virtually extended periodic fields: every component of p (node
+    field, shape (3, n1+1, n2+1, n3+1)) is extended with its own symmetries
+    (identical periods along each axis under Eq. SGO_BCs), transformed by a
+    plain 3D DFT, mapped to u^f by the formulas of Appendix A with the
+    modified frequencies of the scheme (HEX1: Eq. modified_freq_hex1; TETRA2:
+    xi_T2 of Eq. freq_TETRA2), transformed back and restricted to the nodes.
+    Null modes (|xi| = 0, decided in index space) give 0."""
+    if not c0_compatible(kinds):
+        raise ValueError("the C0 operator needs normal-mixed boundary conditions (Eq. SGO_BCs)")
+    Ps = [np.fft.fftn(_extend3(p[q], kinds[q], n)) for q in range(3)]
+    shape = Ps[0].shape
+    xs, at0, atpi = [], [], []
+    for a in range(3):
+        L = shape[a]
+        m = np.arange(L)
+        xs.append(2.0 * np.pi * m / L)
+        at0.append(m == 0)
+        atpi.append((m == L // 2) if L % 2 == 0 else np.zeros(L, dtype=bool))
+    g = [np.meshgrid(*[v for v in arrs], indexing="ij") for arrs in (xs,)][0]
+    s = [np.sin(0.5 * x) for x in g]
+    c = [np.cos(0.5 * x) for x in g]
+    z = np.meshgrid(*at0, indexing="ij")
+    pi = np.meshgrid(*atpi, indexing="ij")
+    for a in range(3):                      # exact values where the index says so
+        s[a] = np.where(z[a], 0.0, np.where(pi[a], 1.0, s[a]))
+        c[a] = np.where(z[a], 1.0, np.where(pi[a], 0.0, c[a]))
+    f = 2.0 / h
+    re = [f * s[0] * c[1] * c[2], f * c[0] * s[1] * c[2], f * c[0] * c[1] * s[2]]
+    allz = z[0] & z[1] & z[2]
+    npi = pi[0].astype(int) + pi[1].astype(int) + pi[2].astype(int)
+    U = [np.zeros(shape, dtype=np.complex128) for _ in range(3)]
+    if scheme == 0:
+        null = allz | (npi >= 2)
+        ok = ~null
+        xi2 = re[0] ** 2 + re[1] ** 2 + re[2] ** 2
+        pd = Ps[0] * re[0] + Ps[1] * re[1] + Ps[2] * re[2]
+        k = (mu0 + lam0) / (2.0 * mu0 + lam0)
+        for q in range(3):
+            U[q][ok] = -(Ps[q][ok] - k * pd[ok] * re[q][ok] / xi2[ok]) / (mu0 * xi2[ok])
+    else:
+        null = allz | (npi == 3)
+        ok = ~null
+        im = [f * c[0] * s[1] * s[2], f * s[0] * c[1] * s[2], f * s[0] * s[1] * c[2]]
+        xi = [re[a] + 1j * im[a] for a in range(3)]           # xi_T2 = conj(xi_T1)
+        xib = [np.conj(v) for v in xi]
+        xi2 = sum(np.abs(v) ** 2 for v in xi)
+        zz = xi[0] ** 2 + xi[1] ** 2 + xi[2] ** 2             # xi . xi
+        zzb = np.conj(zz)
+        ca = 0.5 * (3.0 * mu0 + lam0) * xi2
+        cb = 0.5 * (mu0 + lam0)
+        Ds = ca ** 2 - (cb * np.abs(zz)) ** 2
+        px = Ps[0] * xi[0] + Ps[1] * xi[1] + Ps[2] * xi[2]    # p . xi
+        pxb = Ps[0] * xib[0] + Ps[1] * xib[1] + Ps[2] * xib[2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            p1 = (-ca * px + cb * zz * pxb) / Ds
+            p2 = (cb * zzb * px - ca * pxb) / Ds
+        for q in range(3):
+            U[q][ok] = -(Ps[q][ok] + cb * (p1[ok] * xib[q][ok] + p2[ok] * xi[q][ok])) / (mu0 * xi2[ok])
+    out = np.zeros_like(p)
+    for q in range(3):
+        e = np.fft.ifftn(U[q]).real
+        sl = tuple(slice(0, min(n[a] + 1, shape[a])) for a in range(3))
+        r = e[sl]
+        full = np.zeros(tuple(v + 1 for v in n))
+        full[:r.shape[0], :r.shape[1], :r.shape[2]] = r
+        out[q] = full
+    return out

@@ -56,6 +56,8 @@ class Plan:
         self.exts = [[(_dt.ext_of_bc(bc[q, i, 0]), _dt.ext_of_bc(bc[q, i, 1])) for i in range(3)]
                      for q in range(3)]
         self.kinds = [[_dt.pair_kind(*self.exts[q][i]) for i in range(3)] for q in range(3)]
+        if self.green == 2 and not _green.c0_compatible(self.kinds):
+            raise ValueError("the C0 Green operator needs normal-mixed boundary conditions (Eq. SGO_BCs)")
         self.kept = [_fd.kept_mask(self.exts[q], self.n) for q in range(3)]
         n1, n2, n3 = self.n
         j = [np.arange(self.n[i] + 1) * self.h for i in range(3)]
@@ -87,13 +89,24 @@ class Plan:
         return _fd.applied_divergence(T, self.exts, self.scheme, self.h, self.n)
 
     def L0(self, u):
-        """div_d(R0 : grad_d u) with R0 = B0 (2 mu0 grad u + lambda0 grad u . I)."""
+        """div_d(R0 : grad_d u): R0 = B0 (2 mu0 grad u + lambda0 grad u . I) or
+        2 mu0 (lambda0 = 0) on the non-symmetric gradient; R0 = C0 on the
+        symmetric gradient for the C0 operator (small strain, Sec. 2.6.1)."""
         g = self.grad(u)
+        if self.green == 2:
+            tr = np.trace(g, axis1=-2, axis2=-1)
+            tau0 = self.mu0 * (g + np.swapaxes(g, -1, -2)) + self.lam0 * tr[..., None, None] * np.eye(3)
+            return self.div(tau0)
         lam = self.lam0 if self.green == 0 else 0.0
         tau0 = g * (2.0 * self.mu0 + lam * np.eye(3))    # factor on entry (l, q)
         return self.div(tau0)
 
     def green_apply(self, x):
+        if self.green == 2:
+            u = _green.c0_apply(x, self.kinds, self.n, self.scheme, self.h, self.lam0, self.mu0)
+            for q in range(3):
+                _fd.zero_dismissed(u[q], self.exts[q])
+            return u
         u = np.zeros_like(x)
         for q in range(3):
             xh = _dt.forward_3d(x[q], self.kinds[q])

@@ -344,3 +344,48 @@ def test_applied_traction_equals_fe_face_load(scheme, seed):
     for q in range(3):
         keep = fd.kept_mask(ext3[q], n)
         np.testing.assert_allclose(D[q][keep], (-f[q] / h ** 3 * _face_weight(ext3[q], n))[keep], atol=1e-12)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_c0_green_inverts_L0(scheme):
+    """P5 for the C0 operator (Sec. 2.6.1, Appendix A): on the virtually
+    extended fields its Green operator inverts div_d(C0 : grad^s_d u), the
+    real-space operator with the mirror rules, off the null modes, for every
+    normal-mixed condition pattern (5 pairs per axis for the normal component,
+    the opposite pair for the tangential ones: the 125 cases of Eq. SGO_BCs)."""
+    import workloads as W
+    from oracle.solver import Plan
+    rng = np.random.default_rng(60 + scheme)
+    n = (4, 5, 3)
+    worst = 0.0
+    for choice in itertools.product(range(5), repeat=3):
+        prob = W.random_small_problem(rng, n=n, scheme=scheme, bc=W.normal_mixed_bc(choice))
+        prob.green = W.GREEN_C0
+        prob.lambda0, prob.mu0 = rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0)
+        pl = Plan(prob)
+        x = rng.standard_normal((3,) + tuple(v + 1 for v in n))
+        for q in range(3):
+            fd.zero_dismissed(x[q], pl.exts[q])
+        u = pl.green_apply(x)               # no null-mode content by construction
+        back = pl.green_apply(pl.L0(u))
+        worst = max(worst, float(np.abs(back - u).max() / np.abs(u).max()))
+    assert worst < 1e-11, worst
+
+
+def test_c0_rejects_non_normal_mixed():
+    import workloads as W
+    from oracle.solver import Plan
+    rng = np.random.default_rng(1)
+    bc = W.normal_mixed_bc((1, 0, 2))
+    bc[1, 0] = [W.N, W.N]                   # tangential u_y on the x faces made Neumann like u_x
+    prob = W.random_small_problem(rng, n=(4, 4, 4), bc=bc)
+    prob.green = W.GREEN_C0
+    with pytest.raises(ValueError):
+        Plan(prob)
+    # a bending pattern (every component Dirichlet on the x faces) is not normal-mixed either
+    bc = np.full((3, 3, 2), W.N, dtype=np.int32)
+    bc[:, 0, :] = W.D
+    prob = W.random_small_problem(rng, n=(4, 4, 4), bc=bc)
+    prob.green = W.GREEN_C0
+    with pytest.raises(ValueError):
+        Plan(prob)

@@ -234,3 +234,27 @@ def test_cantilever_beam_theory(scheme):
     assert 0.97 < uy / tip < 1.10
     # the load is carried: the clamped face reacts the applied force
     assert r["macro_sigma"][0][5] != 0.0
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+@pytest.mark.parametrize("seed", range(3))
+def test_c0_fixed_point_equals_b0(scheme, seed):
+    """P10 for the C0 operator: on normal-mixed conditions (Eq. SGO_BCs) the
+    C0-preconditioned iteration converges to the same discrete equilibrium as
+    the B0 one (stress field and <sigma>), and to the direct solve."""
+    rng = np.random.default_rng(400 + seed)
+    choice = rng.integers(0, 5, size=3)
+    if seed == 0:
+        choice = [0, 0, 1]               # the normal-mixed workload: x, y periodic, z faces normal-mixed
+    prob = W.random_small_problem(rng, n=(4, 5, 4), scheme=scheme, bc=W.normal_mixed_bc(choice),
+                                  tol=1e-11)
+    rb = solver.solve(prob)
+    prob.green = W.GREEN_C0
+    rc = solver.solve(prob)
+    assert rb["converged"][0] and rc["converged"][0]
+    scale = np.abs(rb["sig"]).max()
+    np.testing.assert_allclose(rc["sig"], rb["sig"], atol=1e-8 * scale)
+    np.testing.assert_allclose(rc["macro_sigma"], rb["macro_sigma"], atol=1e-9 * scale)
+    eps_d, sig_d, res = _direct_solve(prob)
+    ref = np.stack([sig_d[..., i, j] for (i, j) in solver.VOIGT]).transpose(0, 1, 4, 3, 2)
+    np.testing.assert_allclose(rc["sig"], ref, atol=1e-8 * scale)

@@ -34,7 +34,7 @@ import numpy as np
 
 P, D, N = 0, 1, 2
 HEX1, TETRA2 = 0, 1
-GREEN_B0, GREEN_2MU0 = 0, 1
+GREEN_B0, GREEN_2MU0, GREEN_C0 = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 
 LAW_ISO, LAW_ANISO, LAW_J2, LAW_CP = 0, 1, 2, 3
@@ -436,6 +436,26 @@ def serving_stream(count=500, rate=200.0, sizes=(32, 64, 96, 128, 160, 192), see
         g = int(rng.integers(grains[0], grains[1] + 1))
         out.append(Request(t, cp_polycrystal(rng, nv, g, prec=prec, n_steps=n_steps)))
     return out
+
+
+# extension pairs of the normal component along an axis under the C0
+# operator's normal-mixed conditions (Eq. SGO_BCs); the tangential components
+# take the opposite pair
+NORMAL_MIXED_PAIRS = [(P, P), (N, N), (D, D), (N, D), (D, N)]
+
+
+def normal_mixed_bc(choice) -> np.ndarray:
+    """bc[q][i][a] from one pair per axis for the normal component (indices
+    into NORMAL_MIXED_PAIRS); tangential components get the opposite condition
+    (Dirichlet <-> Neumann), periodic axes stay periodic for all."""
+    opp = {P: P, N: D, D: N}
+    bc = np.zeros((3, 3, 2), dtype=np.int32)
+    for i in range(3):
+        l, r = NORMAL_MIXED_PAIRS[int(choice[i])]
+        for q in range(3):
+            bc[q, i, 0] = l if q == i else opp[l]
+            bc[q, i, 1] = r if q == i else opp[r]
+    return bc
 
 
 def random_small_problem(rng, n=(6, 5, 7), scheme=HEX1, law="iso", green=GREEN_B0,
