@@ -65,10 +65,16 @@ extern "C" {
 #define FM_HEX1   0
 #define FM_TETRA2 1
 
-/* Discrete Green operators of Sec. 2.6: B0 (Sec. 2.6.3, any BCs) and 2mu0
- * (Sec. 2.6.2, lambda0 = 0). */
+/* Discrete Green operators of Sec. 2.6: B0 (Sec. 2.6.3, any BCs), 2mu0
+ * (Sec. 2.6.2, lambda0 = 0) and C0 (Sec. 2.6.1 in its small-strain form of
+ * Appendix A: the isotropic reference medium on the symmetric gradient,
+ * coupling the three components per frequency).  C0 needs normal-mixed
+ * conditions (Eq. SGO_BCs): along every axis the tangential components take
+ * the condition opposite to the normal one's (Dirichlet <-> Neumann on each
+ * face) or all three are periodic; fm_plan_create returns FM_E_BC otherwise. */
 #define FM_GREEN_B0   0
 #define FM_GREEN_2MU0 1
+#define FM_GREEN_C0   2
 
 /* Precision: everything in FP64, or transforms / Green / stencils / laws in
  * FP32 with the displacement accumulator, reductions, the Anderson least
@@ -90,7 +96,7 @@ typedef struct {
   double  h;               /* voxel size */
   int32_t bc[3][3][2];     /* [component q][axis i][face a], a = 0 at the origin */
   int32_t scheme;          /* FM_HEX1 or FM_TETRA2 */
-  int32_t green;           /* FM_GREEN_B0 or FM_GREEN_2MU0 */
+  int32_t green;           /* FM_GREEN_B0, FM_GREEN_2MU0 or FM_GREEN_C0 */
   double  lambda0, mu0;    /* reference medium (Eq. FourierNSGO2) */
   int32_t prec;            /* FM_FP64 or FM_FP32_MIXED */
   double  tol;             /* equilibrium tolerance (Eq. equilibrium_condition) */

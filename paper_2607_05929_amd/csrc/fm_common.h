@@ -126,6 +126,17 @@ struct SolveDev {
   double* out_u;
   double* out_eps;
   double* out_sig;
+  // C0 Green operator (normal-mixed conditions only): the z pass is split
+  // into a forward transform into per-component z-spectral buffers, the
+  // coupled per-frequency apply, and the inverse transform
+  int32_t c0;              // 1 if the plan uses the C0 operator
+  int32_t c0_cplx;         // z-spectral coefficients are complex (some axis periodic)
+  int32_t c0_U[3];         // frequencies per axis, shared by the components
+  int32_t c0_off[3][3];    // [q][axis]: shared frequency index - component's own index
+  int32_t c0_M[3][3];      // [q][axis]: component's own extents
+  int32_t c0_phase[3];     // phase of component q: (-i)^c0_phase[q]
+  void* c0_spec[3];        // z-spectral buffer of component q (M0, M1, M2), x fastest
+  const double* c0_sc[3];  // per axis: sin(xi/2)[U], then cos(xi/2)[U]
 };
 
 // One axis pass of one component of one solve (device).

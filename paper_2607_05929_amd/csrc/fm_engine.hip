@@ -25,6 +25,7 @@
 #include "fm_pass.h"
 #include "fm_space.h"
 #include "fm_wave.h"
+#include "fm_green_c0.h"
 
 using namespace fm;
 
@@ -59,9 +60,13 @@ struct Geometry {
   int cplx[3][3];    // element complex after forward pass on axis a
   int64_t s1[3], s2[3];   // reals of stage-1 / stage-2 buffers per component
   int L[3][3];
-  int F[3][5];       // FFTs per block per pass (generic kernel)
-  int wE[3][5];      // wavefront kernel E = L / 64 per pass, 0 = generic kernel
-  int cols[3][5];    // columns (or rows) per block per pass
+  int F[3][7];       // FFTs per block per pass slot (generic kernel)
+  int wE[3][7];      // wavefront kernel E = L / 64 per pass slot, 0 = generic kernel
+  int cols[3][7];    // columns (or rows) per block per pass slot
+  int c0;            // C0 Green operator: z pass split (slots 5, 6) around the coupled apply
+  int64_t s3[3];     // reals of the z-spectral buffer per component (C0 only)
+  int U[3];          // C0: frequencies per axis shared by the components
+  int ntile_c0;      // C0: tiles of the coupled apply
   int wrap[3];       // axis periodic for some component (halo voxels take the periodic image)
   int sd_nt[3];      // fused stress-divergence tiles per axis
   int sd_zc;         // node layers per fused stress-divergence tile
@@ -124,7 +129,8 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   }
   if (!(d->h > 0)) return fail(FM_E_INVALID_ARG, "voxel size must be positive");
   if (d->scheme != FM_HEX1 && d->scheme != FM_TETRA2) return fail(FM_E_INVALID_ARG, "unknown scheme");
-  if (d->green != FM_GREEN_B0 && d->green != FM_GREEN_2MU0) return fail(FM_E_UNSUPPORTED, "unsupported Green operator");
+  if (d->green != FM_GREEN_B0 && d->green != FM_GREEN_2MU0 && d->green != FM_GREEN_C0)
+    return fail(FM_E_UNSUPPORTED, "unsupported Green operator");
   if (d->prec != FM_FP64 && d->prec != FM_FP32_MIXED) return fail(FM_E_INVALID_ARG, "unknown precision");
   if (!(d->mu0 > 0) || d->lambda0 < 0) return fail(FM_E_INVALID_ARG, "reference medium needs mu0 > 0, lambda0 >= 0");
   if (d->aa_depth < 1 || d->aa_depth > MAX_DEPTH) return fail(FM_E_INVALID_ARG, "aa_depth must be in 1..4");
@@ -138,6 +144,19 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
       if (kind_of(d->bc[q][i][0], d->bc[q][i][1], &g.kinds[q][i]))
         return fail(FM_E_BC, "periodic condition must hold on both opposite faces");
     }
+  g.c0 = d->green == FM_GREEN_C0;
+  if (g.c0) {
+    // Eq. SGO_BCs: along each axis the tangential components take the
+    // transform opposite to the normal one's (the periodic one stays)
+    auto opposite = [](int k) {
+      switch (k) { case K_DCT1: return (int)K_DST1; case K_DST1: return (int)K_DCT1; case K_DCT3: return (int)K_DST3;
+                   case K_DST3: return (int)K_DCT3; default: return (int)K_DFT; }
+    };
+    for (int a = 0; a < 3; ++a)
+      for (int q = 0; q < 3; ++q)
+        if (q != a && g.kinds[q][a] != opposite(g.kinds[a][a]))
+          return fail(FM_E_BC, "the C0 Green operator needs normal-mixed boundary conditions (Eq. SGO_BCs)");
+  }
   g.Nn = (int64_t)g.N[0] * g.N[1] * g.N[2];
   g.Nv = (int64_t)g.n[0] * g.n[1] * g.n[2];
   g.nppv = d->scheme == FM_TETRA2 ? 2 : 1;
@@ -160,6 +179,13 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
     g.F[q][1] = choose_F(g.L[q][1], g.rbytes, 16);
     g.F[q][3] = g.F[q][1];
     g.F[q][2] = choose_F(g.L[q][2], g.rbytes, 16);
+    g.s3[q] = (int64_t)g.M[q][0] * g.M[q][1] * g.M[q][2] * (g.cplx[q][2] ? 2 : 1);
+    // C0 slots 5 (z forward) and 6 (z inverse): generic kernel, strided pencils
+    for (int pass = 5; pass < 7; ++pass) {
+      g.F[q][pass] = g.F[q][2];
+      g.wE[q][pass] = 0;
+      g.cols[q][pass] = !g.cplx[q][1] ? 2 * g.F[q][pass] : g.F[q][pass];
+    }
     for (int pass = 0; pass < 5; ++pass) {
       const int axis = pass == 0 || pass == 4 ? 0 : (pass == 2 ? 2 : 1);
       const int L = g.L[q][axis];
@@ -200,43 +226,70 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   g.ntile_s = g.sd_nt[0] * g.sd_nt[1] * g.sd_nt[2];
   g.ntile_v = (int)cdiv(g.Nv, SPACE_TILE);
   g.ntile_d = (int)cdiv(g.Nn, SPACE_TILE);
+  g.ntile_c0 = 0;
+  if (g.c0) {
+    // shared frequencies per axis: the cosine transform's set for a
+    // DCT-I / DST-I pair (the sine one lacks 0 and pi), else the common one
+    for (int a = 0; a < 3; ++a) {
+      g.U[a] = 0;
+      for (int q = 0; q < 3; ++q) g.U[a] = std::max(g.U[a], g.M[q][a]);
+    }
+    g.ntile_c0 = (int)cdiv((int64_t)g.U[0] * g.U[1] * g.U[2], C0_TILE);
+  }
   return 0;
 }
 
 // Layout of a plan workspace: offsets of every buffer.
 struct Layout {
-  size_t ctrl, log, uf, Dring, dring, specA, specB, mat, mlaw, mtab, state, sig, part_s, part_d, part_g,
-      tw, gtab, group, total;
+  size_t ctrl, log, uf, Dring, dring, specA, specB, specC, c0tab, mat, mlaw, mtab, state, sig, part_s, part_d,
+      part_g, tw, gtab, group, total;
   size_t tw_off[3][3];
   size_t g_off[3][3];   // green tables per comp, axis: s2 (M doubles), c2 (M doubles)
   size_t group_bytes;
 };
 
-// Work lists of a group: 0 voxel tiles (commit), 1 node tiles (Gram),
-// 2..6 the axis passes (x fwd, y fwd, z, y inv, x inv), 7 stress-divergence.
-constexpr int NWL = 8;
+// Work lists of a group: voxel tiles (commit), node tiles (Gram), the pass
+// slots (x fwd, y fwd, fused z, y inv, x inv, and for C0 plans z fwd and
+// z inv), stress-divergence tiles, C0 apply tiles.
+constexpr int NPASS = 7;
+constexpr int WL_VOX = 0, WL_NODE = 1, WL_PASS0 = 2, WL_SDIV = WL_PASS0 + NPASS, WL_C0 = WL_SDIV + 1;
+constexpr int NWL = WL_C0 + 1;
+
+// Pass slots a plan launches: the fused z slot for B0 / 2mu0, the split z
+// slots for C0.
+inline bool slot_used(const Geometry& g, int pass) {
+  if (pass == 2) return !g.c0;
+  if (pass >= 5) return g.c0 != 0;
+  return true;
+}
+inline int slot_axis(int pass) { return pass == 0 || pass == 4 ? 0 : (pass == 1 || pass == 3 ? 1 : 2); }
 
 size_t group_bytes_for(int nsolves, int64_t tiles_total[NWL]);
 
 void tiles_of(const Geometry& g, int64_t t[NWL]) {
-  t[0] = g.ntile_v;
-  t[1] = g.ntile_d;
-  t[7] = g.ntile_s;
-  t[2] = t[3] = t[4] = t[5] = t[6] = 0;
+  for (int k = 0; k < NWL; ++k) t[k] = 0;
+  t[WL_VOX] = g.ntile_v;
+  t[WL_NODE] = g.ntile_d;
+  t[WL_SDIV] = g.ntile_s;
+  t[WL_C0] = g.ntile_c0;
   for (int q = 0; q < 3; ++q) {
     const int rows = g.N[1] * g.N[2];
-    t[2] += cdiv(rows, g.cols[q][0]);
-    t[6] += cdiv(rows, g.cols[q][4]);
-    t[3] += cdiv(g.M[q][0], g.cols[q][1]) * g.N[2];
-    t[5] += cdiv(g.M[q][0], g.cols[q][3]) * g.N[2];
-    t[4] += cdiv(g.M[q][0], g.cols[q][2]) * g.M[q][1];
+    t[WL_PASS0 + 0] += cdiv(rows, g.cols[q][0]);
+    t[WL_PASS0 + 4] += cdiv(rows, g.cols[q][4]);
+    t[WL_PASS0 + 1] += cdiv(g.M[q][0], g.cols[q][1]) * g.N[2];
+    t[WL_PASS0 + 3] += cdiv(g.M[q][0], g.cols[q][3]) * g.N[2];
+    if (!g.c0) t[WL_PASS0 + 2] += cdiv(g.M[q][0], g.cols[q][2]) * g.M[q][1];
+    else {
+      t[WL_PASS0 + 5] += cdiv(g.M[q][0], g.cols[q][5]) * g.M[q][1];
+      t[WL_PASS0 + 6] += cdiv(g.M[q][0], g.cols[q][6]) * g.M[q][1];
+    }
   }
 }
 
 size_t group_bytes_for(int nsolves, int64_t tiles_total[NWL]) {
   size_t b = 0;
   b += align_up(sizeof(SolveDev) * nsolves);
-  b += align_up(sizeof(PassDesc) * nsolves * 15);
+  b += align_up(sizeof(PassDesc) * nsolves * 3 * NPASS);
   for (int i = 0; i < NWL; ++i) b += align_up(sizeof(int2) * std::max<int64_t>(1, tiles_total[i]));
   b += align_up(sizeof(int) * nsolves);
   return b;
@@ -253,6 +306,8 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
   L.dring = take(R * g.depth * 3 * (size_t)g.Nn);
   L.specA = take(R * (size_t)(g.s1[0] + g.s1[1] + g.s1[2]));
   L.specB = take(R * (size_t)(g.s2[0] + g.s2[1] + g.s2[2]));
+  L.specC = g.c0 ? take(R * (size_t)(g.s3[0] + g.s3[1] + g.s3[2])) : 0;
+  L.c0tab = g.c0 ? take(16 * (size_t)(g.U[0] + g.U[1] + g.U[2])) : 0;
   L.mat = take(2 * (size_t)g.Nv);
   L.mlaw = take(4 * (size_t)d->max_materials);
   L.mtab = take(R * MT_STRIDE * (size_t)d->max_materials);
@@ -269,7 +324,7 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
   // column per tile), so that fm_autotune can switch kernels in place
   Geometry gmax = g;
   for (int q = 0; q < 3; ++q)
-    for (int pass = 0; pass < 5; ++pass) gmax.cols[q][pass] = 1;
+    for (int pass = 0; pass < NPASS; ++pass) gmax.cols[q][pass] = 1;
   int64_t t[NWL];
   tiles_of(gmax, t);
   L.group_bytes = group_bytes_for(1, t);
@@ -395,7 +450,7 @@ struct fm_plan {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   SolveDev sd{};           // host image of the device descriptor
-  PassDesc pd[3][5]{};     // host images
+  PassDesc pd[3][NPASS]{};   // host images, per component and pass slot
   bool material_set = false;
   int n_mat = 0;
   int64_t total_iters = 0;
@@ -426,9 +481,9 @@ struct Group {
   PassDesc* P = nullptr;
   int2* wl[NWL]{};     // voxel, node, stress-divergence: whole lists; passes: concatenated buckets
   int64_t nwl[NWL]{};
-  int64_t boff[5][NBUCKET]{};   // start of each bucket inside wl[2 + pass]
-  int64_t bn[5][NBUCKET]{};     // items per bucket
-  size_t blds[5][NBUCKET]{};    // dynamic LDS per bucket
+  int64_t boff[NPASS][NBUCKET]{};   // start of each bucket inside wl[WL_PASS0 + slot]
+  int64_t bn[NPASS][NBUCKET]{};     // items per bucket
+  size_t blds[NPASS][NBUCKET]{};    // dynamic LDS per bucket
   int* ids = nullptr;
   // Captured iteration chunks of 1, 2, 4, ..., 32 iterations, replayed on
   // `stream`; captured on a stream of their own, dropped when the group's
@@ -459,21 +514,24 @@ void fill_pass_descs(fm_plan* p) {
   const Geometry& g = p->g;
   const size_t R = g.rbytes;
   char* ws = p->ws;
-  int64_t offA = 0, offB = 0;
+  int64_t offA = 0, offB = 0, offC = 0;
   for (int q = 0; q < 3; ++q) {
     void* A = ws + p->lay.specA + R * offA;
     void* B = ws + p->lay.specB + R * offB;
+    void* Cz = g.c0 ? ws + p->lay.specC + R * offC : nullptr;
     offA += g.s1[q];
     offB += g.s2[q];
+    offC += g.s3[q];
+    const int M2 = g.M[q][2], c3 = g.cplx[q][2];
     const int M0 = g.M[q][0], M1 = g.M[q][1];
     const int c1 = g.cplx[q][0], c2 = g.cplx[q][1];
     std::vector<int> rad;
-    for (int pass = 0; pass < 5; ++pass) {
+    for (int pass = 0; pass < NPASS; ++pass) {
       PassDesc& d = p->pd[q][pass];
       std::memset(&d, 0, sizeof(d));
       d.solve = 0;
       d.q = q;
-      const int axis = pass == 0 || pass == 4 ? 0 : (pass == 2 ? 2 : 1);
+      const int axis = slot_axis(pass);
       d.kind = g.kinds[q][axis];
       d.n = g.n[axis];
       d.L = g.L[q][axis];
@@ -544,6 +602,26 @@ void fill_pass_descs(fm_plan* p) {
           d.green_lam = p->d.green == FM_GREEN_B0;
           d.h = p->d.h; d.lam0 = p->d.lambda0; d.mu0 = p->d.mu0;
           break;
+        case 5:   // C0: z forward, B (M0, M1, N2) -> C (M0, M1, M2)
+          d.cplx_in = c2; d.cplx_out = c3; d.packed = !c2;
+          d.len_in = g.N[2]; d.len_out = M2;
+          d.n_p0 = M0; d.n_p1 = M1;
+          d.cols = g.cols[q][pass];
+          d.tiles_p0 = (int)cdiv(M0, d.cols);
+          d.in_sa = (int64_t)M0 * M1; d.in_s1 = M0;
+          d.out_sa = (int64_t)M0 * M1; d.out_s1 = M0;
+          d.in = B; d.out = Cz;
+          break;
+        case 6:   // C0: z inverse, C -> B
+          d.cplx_in = c3; d.cplx_out = c2; d.packed = !c2;
+          d.len_in = M2; d.len_out = g.N[2];
+          d.n_p0 = M0; d.n_p1 = M1;
+          d.cols = g.cols[q][pass];
+          d.tiles_p0 = (int)cdiv(M0, d.cols);
+          d.in_sa = (int64_t)M0 * M1; d.in_s1 = M0;
+          d.out_sa = (int64_t)M0 * M1; d.out_s1 = M0;
+          d.in = Cz; d.out = B;
+          break;
       }
     }
   }
@@ -598,6 +676,29 @@ int upload_tables(fm_plan* p) {
       HIPCHK(hipMemcpyAsync(ws + p->lay.g_off[q][a], buf.data(), buf.size(), hipMemcpyHostToDevice, p->stream));
       HIPCHK(hipStreamSynchronize(p->stream));
     }
+  if (g.c0) {
+    // C0: sin(xi/2) and cos(xi/2) (signed: a full periodic axis reaches
+    // xi > pi) of each shared frequency per axis, exact 0 / 1 at xi = 0, pi
+    std::vector<double> t;
+    for (int a = 0; a < 3; ++a) {
+      const int n = g.n[a], U = g.U[a];
+      const int kn = g.kinds[a][a];   // the normal component's transform fixes the frequency set
+      std::vector<double> sv(U), cv(U);
+      for (int u = 0; u < U; ++u) {
+        long double xi;
+        bool z = false, pi = false;
+        if (kn == K_DFT) { xi = 2.0L * M_PIl * u / n; z = u == 0; pi = 2 * u == n; }
+        else if (kn == K_DCT1 || kn == K_DST1) { xi = M_PIl * u / n; z = u == 0; pi = u == n; }
+        else xi = M_PIl * (u + 0.5L) / n;
+        sv[u] = z ? 0.0 : pi ? 1.0 : (double)sinl(0.5L * xi);
+        cv[u] = z ? 1.0 : pi ? 0.0 : (double)cosl(0.5L * xi);
+      }
+      t.insert(t.end(), sv.begin(), sv.end());
+      t.insert(t.end(), cv.begin(), cv.end());
+    }
+    HIPCHK(hipMemcpyAsync(ws + p->lay.c0tab, t.data(), 8 * t.size(), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  }
   return 0;
 }
 
@@ -629,7 +730,7 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   G.plastic = 0;
   for (int i = 0; i < ns; ++i) G.plastic |= plans[i]->d.with_state ? 1 : 0;
   G.stream = stream;
-  int64_t t[NWL] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t t[NWL] = {};
   for (int i = 0; i < ns; ++i) {
     if (plans[i]->d.prec != G.prec) return fail(FM_E_INVALID_ARG, "a batch must share one precision");
     int64_t ti[NWL];
@@ -640,15 +741,15 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   if (need > bytes) return fail(FM_E_WORKSPACE, "group workspace too small");
   size_t o = 0;
   G.S = (SolveDev*)(dev + o); o += align_up(sizeof(SolveDev) * ns);
-  G.P = (PassDesc*)(dev + o); o += align_up(sizeof(PassDesc) * ns * 15);
+  G.P = (PassDesc*)(dev + o); o += align_up(sizeof(PassDesc) * ns * 3 * NPASS);
   for (int k = 0; k < NWL; ++k) { G.wl[k] = (int2*)(dev + o); o += align_up(sizeof(int2) * std::max<int64_t>(1, t[k])); }
   G.ids = (int*)(dev + o);
   std::vector<SolveDev> S(ns);
-  std::vector<PassDesc> P(ns * 15);
-  std::vector<int2> wl[3];
-  std::vector<int2> pb[5][NBUCKET];
+  std::vector<PassDesc> P((size_t)ns * 3 * NPASS);
+  std::vector<int2> wl[4];          // voxel, node, stress-divergence, C0 apply tiles
+  std::vector<int2> pb[NPASS][NBUCKET];
   std::vector<int> ids(ns);
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < NPASS; ++k)
     for (int b = 0; b < NBUCKET; ++b) G.blds[k][b] = 0;
   for (int i = 0; i < ns; ++i) {
     fm_plan* p = plans[i];
@@ -657,14 +758,16 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
     for (int ty = 0; ty < p->g.ntile_v; ++ty) wl[0].push_back(make_int2(i, ty));
     for (int ty = 0; ty < p->g.ntile_d; ++ty) wl[1].push_back(make_int2(i, ty));
     for (int ty = 0; ty < p->g.ntile_s; ++ty) wl[2].push_back(make_int2(i, ty));
+    for (int ty = 0; ty < p->g.ntile_c0; ++ty) wl[3].push_back(make_int2(i, ty));
     for (int q = 0; q < 3; ++q)
-      for (int pass = 0; pass < 5; ++pass) {
+      for (int pass = 0; pass < NPASS; ++pass) {
         PassDesc d = p->pd[q][pass];
         d.solve = i;
-        const int di = i * 15 + q * 5 + pass;
+        const int di = (i * 3 + q) * NPASS + pass;
         P[di] = d;
+        if (!slot_used(p->g, pass)) continue;
         const int64_t ntiles = pass == 0 || pass == 4 ? d.tiles_p0 : (int64_t)d.tiles_p0 * d.n_p1;
-        const int pk = pass == 0 ? 0 : pass == 1 ? 1 : pass == 2 ? 2 : pass == 3 ? 3 : 4;   // launch order slot
+        const int pk = pass;   // launch order slot
         const int E = p->g.wE[q][pass];
         const int b = bucket_of(E, d.kind, d.packed);
         if (E == 8 && (d.cols != (d.packed ? 2 * WAVE_PENCILS : WAVE_PENCILS) || d.L != 512))
@@ -674,7 +777,7 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
         const size_t R = p->g.rbytes;
         if (E) {
           // staging of phase A (input tile) and phase C (output tile), sized separately
-          const int mode = pass == 2 ? 2 : (pass == 3 || pass == 4) ? 1 : 0;
+          const int mode = pass == 2 ? 2 : (pass == 3 || pass == 4 || pass == 6) ? 1 : 0;
           const bool half = d.packed && d.kind == K_DFT;
           int j0, cnt;
           raw_range(d.kind, d.n, j0, cnt);
@@ -691,8 +794,8 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
         G.blds[pk][b] = std::max(G.blds[pk][b], lds);
       }
   }
-  std::vector<int2> pl[5];
-  for (int k = 0; k < 5; ++k) {
+  std::vector<int2> pl[NPASS];
+  for (int k = 0; k < NPASS; ++k) {
     int64_t off = 0;
     for (int b = 0; b < NBUCKET; ++b) {
       G.boff[k][b] = off;
@@ -702,11 +805,12 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
       off += G.bn[k][b];
     }
   }
-  for (int k = 0; k < 3; ++k) xcd_order(wl[k], 0, wl[k].size());
+  for (int k = 0; k < 4; ++k) xcd_order(wl[k], 0, wl[k].size());
   HIPCHK(hipMemcpyAsync(G.S, S.data(), sizeof(SolveDev) * ns, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(G.P, P.data(), sizeof(PassDesc) * ns * 15, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(G.P, P.data(), sizeof(PassDesc) * P.size(), hipMemcpyHostToDevice, stream));
   for (int k = 0; k < NWL; ++k) {
-    const std::vector<int2>& v = k < 2 ? wl[k] : (k < 7 ? pl[k - 2] : wl[2]);
+    const std::vector<int2>& v = k == WL_VOX ? wl[0] : k == WL_NODE ? wl[1] : k == WL_SDIV ? wl[2]
+                                 : k == WL_C0 ? wl[3] : pl[k - WL_PASS0];
     G.nwl[k] = (int64_t)v.size();
     if (!v.empty())
       HIPCHK(hipMemcpyAsync(G.wl[k], v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, stream));
@@ -925,7 +1029,7 @@ void launch_w8_kind(int kind, int packed, dim3 grid, size_t lds, hipStream_t st,
 
 template <typename R, int MODE, int XP>
 int launch_bucket(const Group& G, int pk, int b) {
-  const int2* wl = G.wl[2 + pk] + G.boff[pk][b];
+  const int2* wl = G.wl[WL_PASS0 + pk] + G.boff[pk][b];
   const dim3 grid((unsigned)G.bn[pk][b]);
   const size_t lds = G.blds[pk][b];
   hipStream_t st = G.stream;
@@ -957,8 +1061,20 @@ int launch_pass(const Group& G, int pk, int b) {
     case 1: return launch_bucket<R, 0, 0>(G, pk, b);
     case 2: return launch_bucket<R, 2, 0>(G, pk, b);
     case 3: return launch_bucket<R, 1, 0>(G, pk, b);
+    case 5: return launch_bucket<R, 0, 0>(G, pk, b);
+    case 6: return launch_bucket<R, 1, 0>(G, pk, b);
     default: return launch_bucket<R, 1, 1>(G, pk, b);
   }
+}
+
+template <typename R>
+int launch_slot(const Group& G, int pk) {
+  for (int b = 0; b < NBUCKET; ++b)
+    if (G.bn[pk][b]) {
+      const int rc = launch_pass<R>(G, pk, b);
+      if (rc) return rc;
+    }
+  return 0;
 }
 
 // Kernel k (0..9) of the iteration sequence.
@@ -967,33 +1083,41 @@ int launch_one(const Group& G, int k) {
   hipStream_t st = G.stream;
   switch (k) {
     case 0:
-      if (!G.nwl[7]) break;
+      if (!G.nwl[WL_SDIV]) break;
       // FP32 groups launch the FP32 and the FP64 real-space kernel; each
       // solve's control block picks the one that works (the other returns)
       if (G.plastic) {
         // plastic solves: the law once per voxel (one thread each), then the
         // fused kernel reads those stresses
-        if (G.nwl[0])
-          hipLaunchKernelGGL((k_commit<R, 1, 1>), dim3(G.nwl[0] * (SPACE_TILE / 256)), dim3(256), 0, st, G.S, G.wl[0]);
-        hipLaunchKernelGGL((k_sdiv<R, 1>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[7]);
+        if (G.nwl[WL_VOX])
+          hipLaunchKernelGGL((k_commit<R, 1, 1>), dim3(G.nwl[WL_VOX] * (SPACE_TILE / 256)), dim3(256), 0, st, G.S, G.wl[WL_VOX]);
+        hipLaunchKernelGGL((k_sdiv<R, 1>), dim3(G.nwl[WL_SDIV]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[WL_SDIV]);
         if constexpr (sizeof(R) == 4)
-          hipLaunchKernelGGL((k_sdiv<R, 1, double>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(8), st, G.S, G.wl[7]);
+          hipLaunchKernelGGL((k_sdiv<R, 1, double>), dim3(G.nwl[WL_SDIV]), dim3(256), sdiv_lds_bytes(8), st, G.S, G.wl[WL_SDIV]);
       } else {
-        hipLaunchKernelGGL((k_sdiv<R, 0>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[7]);
+        hipLaunchKernelGGL((k_sdiv<R, 0>), dim3(G.nwl[WL_SDIV]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[WL_SDIV]);
         if constexpr (sizeof(R) == 4)
-          hipLaunchKernelGGL((k_sdiv<R, 0, double>), dim3(G.nwl[7]), dim3(256), sdiv_lds_bytes(8), st, G.S, G.wl[7]);
+          hipLaunchKernelGGL((k_sdiv<R, 0, double>), dim3(G.nwl[WL_SDIV]), dim3(256), sdiv_lds_bytes(8), st, G.S, G.wl[WL_SDIV]);
       }
       break;
     case 1: hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
-    case 2: if (G.nwl[1]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[1]), dim3(256), 0, st, G.S, G.wl[1]); break;
+    case 2: if (G.nwl[WL_NODE]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[WL_NODE]), dim3(256), 0, st, G.S, G.wl[WL_NODE]); break;
     case 3: hipLaunchKernelGGL(k_alpha, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
+    case 6: {
+      // z: the fused forward / Green / inverse pass of B0 and 2mu0 plans;
+      // for C0 plans the forward pass, the coupled apply, the inverse pass
+      int rc = launch_slot<R>(G, 2);
+      if (!rc) rc = launch_slot<R>(G, 5);
+      if (rc) return rc;
+      if (G.nwl[WL_C0])
+        hipLaunchKernelGGL(k_green_c0<R>, dim3(G.nwl[WL_C0]), dim3(C0_TILE), 0, st, G.S, G.wl[WL_C0]);
+      rc = launch_slot<R>(G, 6);
+      if (rc) return rc;
+      break;
+    }
     default: {
-      const int pk = k - 4;    // 0 x fwd, 1 y fwd, 2 z, 3 y inv, 4 x inv
-      for (int b = 0; b < NBUCKET; ++b)
-        if (G.bn[pk][b]) {
-          const int rc = launch_pass<R>(G, pk, b);
-          if (rc) return rc;
-        }
+      const int rc = launch_slot<R>(G, k - 4);    // 4 x fwd, 5 y fwd, 7 y inv, 8 x inv
+      if (rc) return rc;
       break;
     }
   }
@@ -1057,8 +1181,8 @@ int launch_iterations(Group& G, int count) {
 template <typename R>
 int launch_commit_t(fm_plan* p) {
   const Group& G = *p->self;
-  if (G.plastic) hipLaunchKernelGGL((k_commit<R, 1>), dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0]);
-  else hipLaunchKernelGGL((k_commit<R, 0>), dim3(G.nwl[0]), dim3(256), 0, G.stream, G.S, G.wl[0]);
+  if (G.plastic) hipLaunchKernelGGL((k_commit<R, 1>), dim3(G.nwl[WL_VOX]), dim3(256), 0, G.stream, G.S, G.wl[WL_VOX]);
+  else hipLaunchKernelGGL((k_commit<R, 0>), dim3(G.nwl[WL_VOX]), dim3(256), 0, G.stream, G.S, G.wl[WL_VOX]);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -1335,6 +1459,28 @@ int fm_plan_create(const fm_plan_desc* desc, void* d_workspace, size_t ws_bytes,
     s.wrap[i] = g.wrap[i];
     for (int q = 0; q < 3; ++q)
       if (g.wrap[i] && g.kinds[q][i] != K_DFT) s.mixed_wrap = 1;
+  }
+  s.c0 = g.c0;
+  if (g.c0) {
+    s.c0_cplx = g.cplx[0][2];
+    int64_t offC = 0;
+    size_t toff = 0;
+    for (int a = 0; a < 3; ++a) {
+      s.c0_U[a] = g.U[a];
+      s.c0_sc[a] = (const double*)(ws + p->lay.c0tab + 8 * toff);
+      toff += 2 * (size_t)g.U[a];
+    }
+    for (int q = 0; q < 3; ++q) {
+      s.c0_spec[q] = ws + p->lay.specC + (size_t)g.rbytes * offC;
+      offC += g.s3[q];
+      int sines = 0;
+      for (int a = 0; a < 3; ++a) {
+        s.c0_M[q][a] = g.M[q][a];
+        s.c0_off[q][a] = g.U[a] - g.M[q][a] == 2 ? 1 : 0;    // DST-I inside the DCT-I frequency set
+        sines += g.kinds[q][a] == K_DST1 || g.kinds[q][a] == K_DST3;
+      }
+      s.c0_phase[q] = sines & 3;
+    }
   }
   fill_pass_descs(p.get());
   rc = upload_tables(p.get());
