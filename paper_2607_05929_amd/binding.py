@@ -443,7 +443,9 @@ class Server:
         t = C.c_uint64()
         check(lib().fm_server_submit(self.handle, C.byref(req), float(now_s), C.byref(t)),
               "fm_server_submit")
-        self.keep[t.value] = (macro, iters, prob)
+        # the library copies the request's inputs; it writes its results into
+        # these two host arrays when the solve completes
+        self.keep[t.value] = (macro, iters)
         return t.value
 
     def step(self, iters, now_s):
@@ -457,8 +459,12 @@ class Server:
         return int(st.value), float(lat.value)
 
     def result(self, ticket):
-        macro, iters, _ = self.keep[ticket]
+        macro, iters = self.keep[ticket]
         return {"macro_sigma": macro, "iters": iters.tolist()}
+
+    def release(self, ticket):
+        """Drop the host result buffers of a completed request."""
+        return self.keep.pop(ticket)
 
     def stats(self):
         s = Stats()

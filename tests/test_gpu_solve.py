@@ -280,3 +280,69 @@ def test_autotune_then_solve_matches_oracle(B, inclusion32):
     es = rel_err(r["sig"], ref["sig"])
     print(f"autotuned inclusion32 macro err {e:.2e} sigma err {es:.2e}", flush=True)
     assert e < 1e-7 and es < 1e-6
+
+
+def test_server_admission_near_full_arena(B):
+    """An arena that holds one request's workspace but not its batch
+    descriptors refuses the request at submission; an arena with room for one
+    request at a time (plus descriptors) serves a stream of them one after
+    the other without error."""
+    import ctypes as C
+    probs = _batch_problems()[:3]
+    for p in probs:
+        p.n = (16, 16, 16)
+        p.mat_id = np.zeros((16, 16, 16), dtype=np.int32)
+        p.mat_id[4:10, 4:10, 4:10] = 1
+    d = B.plan_desc(probs[0], W.FP32_MIXED)
+    ws = int(B.lib().fm_workspace_bytes(C.byref(d)))
+    stage = 4 * 16 ** 3
+    tight = B.Server(arena_bytes=ws + stage + 4096, max_active=4)
+    with pytest.raises(B.FmError, match="never fit"):
+        tight.submit(probs[0], arrival_s=0.0, prec=W.FP32_MIXED)
+    tight.close()
+    srv = B.Server(arena_bytes=ws + stage + (2 << 20), max_active=4)
+    tickets = [srv.submit(p, arrival_s=0.0, prec=W.FP32_MIXED) for p in probs]
+    for _ in range(4000):
+        srv.step(8, 0.0)
+        if all(srv.poll(t)[0] == 2 for t in tickets):
+            break
+    st = srv.stats()
+    print(f"near-full arena stats {st}", flush=True)
+    assert st["completed"] == 3 and st["arena_in_use"] == 0
+    for t, p in zip(tickets, probs):
+        alone = B.solve(p, prec=W.FP32_MIXED, fields=False)
+        np.testing.assert_array_equal(srv.result(t)["macro_sigma"], alone["macro_sigma"])
+    srv.close()
+
+
+def test_server_cp_mix_equals_alone(B):
+    """The served law: crystal-plasticity torsion-bending requests of
+    different sizes and grain counts, arriving while others run, each give
+    the result of their lone solve (same device arithmetic, bitwise) and
+    converge every increment."""
+    rng = np.random.default_rng(5)
+    probs = [W.cp_polycrystal(rng, nv, g, prec=W.FP32_MIXED, n_steps=3, eps_max=4e-3)
+             for nv, g in ((8, 3), (12, 5), (10, 4), (16, 6))]
+    srv = B.Server(arena_bytes=512 << 20, max_active=3)
+    tickets = []
+    now = 0.0
+    for k, p in enumerate(probs):
+        tickets.append(srv.submit(p, arrival_s=now, prec=W.FP32_MIXED))
+        srv.step(3, now)                     # later requests arrive while earlier ones run
+        now += 0.001
+    for _ in range(4000):
+        srv.step(4, now)
+        now += 0.001
+        if all(srv.poll(t)[0] == 2 for t in tickets):
+            break
+    st = srv.stats()
+    print(f"cp server stats {st}", flush=True)
+    assert st["completed"] == len(probs)
+    for t, p in zip(tickets, probs):
+        alone = B.solve(p, prec=W.FP32_MIXED, fields=False)
+        got = srv.result(t)
+        print(f"cp served n={p.n} iters {got['iters']} alone {alone['iters']}", flush=True)
+        assert all(alone["converged"])
+        assert got["iters"] == alone["iters"]
+        np.testing.assert_array_equal(got["macro_sigma"], alone["macro_sigma"])
+    srv.close()
