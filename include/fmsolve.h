@@ -249,7 +249,10 @@ int fm_profile_iterations(fm_plan* plan, const fm_load_step* step, int32_t n_ite
  * Results are identical in both modes.  Returns FM_OK. */
 int fm_set_graph_launch(int enable);
 
-/* Transform-kernel autotuner (per plan): for each of the five axis passes
+/* Transform-kernel autotuner (per plan).  Choices are kept for the process
+ * per transform signature (grid, per-component transform kinds, precision,
+ * scheme, Green operator): a plan whose signature was tuned before takes the
+ * stored choice without timing (ms then holds -1 everywhere).  Otherwise, for each of the five axis passes
  * (x forward, y forward, z forward+Green+inverse, y inverse, x inverse),
  * times n_iter iterations of *step with every applicable candidate kernel --
  * 0 the wavefront kernel (pencil lengths 64E), 1..3 the generic LDS kernel

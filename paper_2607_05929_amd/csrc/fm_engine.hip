@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -475,6 +476,7 @@ constexpr int E_of_bucket[NBUCKET] = {0, 1, 2, 3, 4, 5, 6, 8, 12, 16, 8, 8, 8, 8
 struct Group {
   int prec = 0;
   int plastic = 0;    // any solve with J2 / CP internal variables
+  int trac = 0;       // some load path of the group applies tractions (real-space kernel with D*)
   int ns = 0;
   hipStream_t stream = nullptr;
   SolveDev* S = nullptr;
@@ -507,6 +509,22 @@ struct Group {
 // Iteration chunks go through captured HIP graphs unless switched off
 // (fm_set_graph_launch).
 bool g_use_graphs = true;
+
+bool has_traction(const fm_load_step* st, int n) {
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < 18; ++i)
+      if ((&st[k].traction[0][0][0])[i] != 0) return true;
+  return false;
+}
+
+// Select the real-space kernel with (t) or without the traction term; the
+// captured chunks hold one of them, so they are dropped on a change.
+void set_trac(Group& G, bool t) {
+  if (G.trac != (int)t) {
+    G.drop_graphs();
+    G.trac = t;
+  }
+}
 
 namespace {
 
@@ -950,6 +968,32 @@ hipError_t set_wave_lds(int big) {
   }
 }
 
+template <typename R, int TR>
+hipError_t set_sdiv_lds_tr() {
+  hipError_t r;
+  if ((r = hipFuncSetAttribute((const void*)k_sdiv<R, 0, R, TR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sdiv_lds_bytes(sizeof(R)))))
+    return r;
+  if ((r = hipFuncSetAttribute((const void*)k_sdiv<R, 1, R, TR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sdiv_lds_bytes(sizeof(R)))))
+    return r;
+  if constexpr (sizeof(R) == 4) {
+    if ((r = hipFuncSetAttribute((const void*)k_sdiv<R, 0, double, TR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sdiv_lds_bytes(8))))
+      return r;
+    return hipFuncSetAttribute((const void*)k_sdiv<R, 1, double, TR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sdiv_lds_bytes(8));
+  }
+  return hipSuccess;
+}
+
+template <typename R>
+hipError_t set_sdiv_lds() {
+  hipError_t r = set_sdiv_lds_tr<R, 0>();
+  if (r) return r;
+  return set_sdiv_lds_tr<R, 1>();
+}
+
 template <typename R>
 int set_lds_limits() {
   static bool done = false;
@@ -978,16 +1022,7 @@ int set_lds_limits() {
   }
   HIPCHK((set_wave_lds<R, 12>(big)));
   HIPCHK((set_wave_lds<R, 16>(big)));
-  HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)sdiv_lds_bytes(sizeof(R))));
-  HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)sdiv_lds_bytes(sizeof(R))));
-  if constexpr (sizeof(R) == 4) {
-    HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 0, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)sdiv_lds_bytes(8)));
-    HIPCHK(hipFuncSetAttribute((const void*)k_sdiv<R, 1, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)sdiv_lds_bytes(8)));
-  }
+  HIPCHK(set_sdiv_lds<R>());
   done = true;
   return 0;
 }
@@ -1077,6 +1112,39 @@ int launch_slot(const Group& G, int pk) {
   return 0;
 }
 
+// Blocks of the FP64 real-space kernel of FP32 groups: two per compute unit,
+// walking the tile list (a multiple of 8, so each stays on one XCD).
+inline int rs64_grid(const Group& G) {
+  const int cu = g_num_cu > 0 ? g_num_cu : 256;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(G.nwl[WL_SDIV], 2 * cu));
+}
+
+template <typename R, int TR>
+int launch_sdiv(const Group& G) {
+  hipStream_t st = G.stream;
+  const int nw = (int)G.nwl[WL_SDIV];
+  // FP32 groups launch the FP32 and the FP64 real-space kernel; each solve's
+  // control block picks the one that works (the other returns)
+  if (G.plastic) {
+    // plastic solves: the law once per voxel (one thread each), then the
+    // fused kernel reads those stresses
+    if (G.nwl[WL_VOX])
+      hipLaunchKernelGGL((k_commit<R, 1, 1>), dim3(G.nwl[WL_VOX] * (SPACE_TILE / 256)), dim3(256), 0, st, G.S,
+                         G.wl[WL_VOX]);
+    hipLaunchKernelGGL((k_sdiv<R, 1, R, TR>), dim3(nw), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[WL_SDIV], nw);
+    if constexpr (sizeof(R) == 4)
+      hipLaunchKernelGGL((k_sdiv<R, 1, double, TR>), dim3(rs64_grid(G)), dim3(256), sdiv_lds_bytes(8), st, G.S,
+                         G.wl[WL_SDIV], nw);
+  } else {
+    hipLaunchKernelGGL((k_sdiv<R, 0, R, TR>), dim3(nw), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[WL_SDIV], nw);
+    if constexpr (sizeof(R) == 4)
+      hipLaunchKernelGGL((k_sdiv<R, 0, double, TR>), dim3(rs64_grid(G)), dim3(256), sdiv_lds_bytes(8), st, G.S,
+                         G.wl[WL_SDIV], nw);
+  }
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 // Kernel k (0..9) of the iteration sequence.
 template <typename R>
 int launch_one(const Group& G, int k) {
@@ -1084,22 +1152,8 @@ int launch_one(const Group& G, int k) {
   switch (k) {
     case 0:
       if (!G.nwl[WL_SDIV]) break;
-      // FP32 groups launch the FP32 and the FP64 real-space kernel; each
-      // solve's control block picks the one that works (the other returns)
-      if (G.plastic) {
-        // plastic solves: the law once per voxel (one thread each), then the
-        // fused kernel reads those stresses
-        if (G.nwl[WL_VOX])
-          hipLaunchKernelGGL((k_commit<R, 1, 1>), dim3(G.nwl[WL_VOX] * (SPACE_TILE / 256)), dim3(256), 0, st, G.S, G.wl[WL_VOX]);
-        hipLaunchKernelGGL((k_sdiv<R, 1>), dim3(G.nwl[WL_SDIV]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[WL_SDIV]);
-        if constexpr (sizeof(R) == 4)
-          hipLaunchKernelGGL((k_sdiv<R, 1, double>), dim3(G.nwl[WL_SDIV]), dim3(256), sdiv_lds_bytes(8), st, G.S, G.wl[WL_SDIV]);
-      } else {
-        hipLaunchKernelGGL((k_sdiv<R, 0>), dim3(G.nwl[WL_SDIV]), dim3(256), sdiv_lds_bytes(sizeof(R)), st, G.S, G.wl[WL_SDIV]);
-        if constexpr (sizeof(R) == 4)
-          hipLaunchKernelGGL((k_sdiv<R, 0, double>), dim3(G.nwl[WL_SDIV]), dim3(256), sdiv_lds_bytes(8), st, G.S, G.wl[WL_SDIV]);
-      }
-      break;
+      if (G.trac) return launch_sdiv<R, 1>(G);
+      return launch_sdiv<R, 0>(G);
     case 1: hipLaunchKernelGGL(k_control, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
     case 2: if (G.nwl[WL_NODE]) hipLaunchKernelGGL(k_gram<R>, dim3(G.nwl[WL_NODE]), dim3(256), 0, st, G.S, G.wl[WL_NODE]); break;
     case 3: hipLaunchKernelGGL(k_alpha, dim3(G.ns), dim3(256), 0, st, G.S, G.ids); break;
@@ -1547,6 +1601,7 @@ int fm_solve(fm_plan* p, const fm_load_step* steps, int32_t n_steps, fm_outputs*
   if (!p || !steps || n_steps < 1) return fail(FM_E_INVALID_ARG, "null plan or empty load path");
   if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called before fm_solve");
   if (int rc = check_tractions(p->d, steps, n_steps)) return rc;
+  set_trac(*p->self, has_traction(steps, n_steps));
   if (log) log->count = 0;
   p->total_iters = 0;
   int result = FM_OK;
@@ -1611,6 +1666,8 @@ int fm_apply_green(fm_plan* p, const double* d_x, double* d_w) {
 int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double* d_D, double* err, double* macro) {
   if (!p || !step || !d_uf || !d_D) return fail(FM_E_INVALID_ARG, "null argument");
   if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called first");
+  if (int rc = check_tractions(p->d, step, 1)) return rc;
+  set_trac(*p->self, has_traction(step, 1));
   int rc = begin_step(p, *step, 0, nullptr);
   if (rc) return rc;
   const int64_t n3 = 3 * p->g.Nn;
@@ -1640,6 +1697,8 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
 int fm_profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, double* ms) {
   if (!p || !step || n_iter < 1 || !ms) return fail(FM_E_INVALID_ARG, "null argument");
   if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called first");
+  if (int rc = check_tractions(p->d, step, 1)) return rc;
+  set_trac(*p->self, has_traction(step, 1));
   int rc = begin_step(p, *step, 0, nullptr);
   if (rc) return rc;
   Ctrl c;
@@ -1684,9 +1743,45 @@ int fm_profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, 
   return FM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Transform choices already tuned in this process, per signature: grid,
+// per-component transform kinds, precision, scheme, Green operator.
+std::mutex g_tune_mu;
+std::map<std::string, std::array<int, 5>> g_tune_cache;
+
+std::string tune_key(const fm_plan* p) {
+  std::string k;
+  for (int i = 0; i < 3; ++i) k += std::to_string(p->g.n[i]) + ",";
+  for (int q = 0; q < 3; ++q)
+    for (int a = 0; a < 3; ++a) k += std::to_string(p->g.kinds[q][a]);
+  k += "/" + std::to_string(p->d.prec) + "/" + std::to_string(p->d.scheme) + "/" + std::to_string(p->d.green);
+  return k;
+}
+}  // namespace
+
+extern "C" {
+
 int fm_autotune(fm_plan* p, const fm_load_step* step, int32_t n_iter, int32_t* choice, double* ms) {
   if (!p || !step || n_iter < 1) return fail(FM_E_INVALID_ARG, "null argument");
   if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called first");
+  const std::string key = tune_key(p);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      Geometry g = p->g;
+      for (int pass = 0; pass < 5; ++pass) {
+        if (it->second[pass] >= 0) apply_choice(g, pass, it->second[pass]);
+        if (choice) choice[pass] = it->second[pass];
+      }
+      if (ms)
+        for (int i = 0; i < N_TUNE * 5; ++i) ms[i] = -1.0;
+      p->g = g;
+      return rebuild_plan_group(p);
+    }
+  }
   const Geometry saved = p->g;
   int best[5];
   double best_ms[5];
@@ -1715,9 +1810,15 @@ int fm_autotune(fm_plan* p, const fm_load_step* step, int32_t n_iter, int32_t* c
     }
   }
   Geometry g = saved;
+  std::array<int, 5> keep;
   for (int pass = 0; pass < 5; ++pass) {
     if (best[pass] >= 0) apply_choice(g, pass, best[pass]);
     if (choice) choice[pass] = best[pass];
+    keep[pass] = best[pass];
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = keep;
   }
   p->g = g;
   return rebuild_plan_group(p);

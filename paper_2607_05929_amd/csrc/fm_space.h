@@ -353,7 +353,6 @@ __device__ __forceinline__ void column_partials(const SolveDev& s, const R (&sp)
 template <typename R>
 struct NodeXY {
   R fq[3];
-  R tq[3];      // D* of the applied tractions of the x and y faces the node lies on
   int drop;
 };
 
@@ -369,21 +368,24 @@ __device__ __forceinline__ R dstar(const FM_GLOBAL Ctrl* C, int i, int a, int q)
   else return (R)C->dstar[(i * 2 + a) * 3 + q];
 }
 
+// D*_q of the applied tractions at node (J0, J1, J2): the sum over the
+// loaded faces the node lies on (read only when some face is loaded).
 template <typename R>
-__device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, const FM_GLOBAL Ctrl* C, int J0, int J1) {
+__device__ __forceinline__ R node_dstar(const SolveDev& s, const FM_GLOBAL Ctrl* C, int J0, int J1, int J2, int q) {
+  R t = 0;
+  if (J0 == 0) t += dstar<R>(C, 0, 0, q);
+  if (J0 == s.n[0]) t += dstar<R>(C, 0, 1, q);
+  if (J1 == 0) t += dstar<R>(C, 1, 0, q);
+  if (J1 == s.n[1]) t += dstar<R>(C, 1, 1, q);
+  if (J2 == 0) t += dstar<R>(C, 2, 0, q);
+  if (J2 == s.n[2]) t += dstar<R>(C, 2, 1, q);
+  return t;
+}
+
+template <typename R>
+__device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, int J0, int J1) {
   NodeXY<R> r;
   r.drop = 0;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    R t = 0;
-    if (C->has_trac) {
-      if (J0 == 0) t += dstar<R>(C, 0, 0, q);
-      if (J0 == s.n[0]) t += dstar<R>(C, 0, 1, q);
-      if (J1 == 0) t += dstar<R>(C, 1, 0, q);
-      if (J1 == s.n[1]) t += dstar<R>(C, 1, 1, q);
-    }
-    r.tq[q] = t;
-  }
   const int J[2] = {J0, J1};
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -410,10 +412,10 @@ __device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, const FM_GLOBAL 
 // Divergence at the node of layer J2 (z factor fz per component: doubling on
 // a reflecting z face, 0 where not kept along z) from the column partials of
 // its four voxel columns; D written through Dn (this node in component 0).
-template <typename CT, typename R>
+template <typename CT, typename R, int TR>
 __device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int ly, const NodeXY<CT>& nxy,
-                                         const CT (&fz)[3], const CT (&tz)[3], FM_GLOBAL R* Dn, int64_t Nn,
-                                         CT& accD) {
+                                         const CT (&fz)[3], FM_GLOBAL R* Dn, int64_t Nn, CT& accD,
+                                         const SolveDev& s, const FM_GLOBAL Ctrl* C, int J0, int J1, int J2) {
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     CT D = 0;
@@ -425,7 +427,8 @@ __device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int l
         D += ((nxy.drop >> (q * 4 + b1 * 2 + b0)) & 1) ? (CT)0 : t;
       }
     const CT f = nxy.fq[q] * fz[q];
-    const CT Dq = D * f + (f != (CT)0 ? nxy.tq[q] + tz[q] : (CT)0);
+    CT Dq = D * f;
+    if (TR && f != (CT)0) Dq += node_dstar<CT>(s, C, J0, J1, J2, q);
     accD += Dq * Dq;
     Dn[q * Nn] = (R)Dq;
   }
@@ -441,9 +444,8 @@ __host__ __device__ inline size_t sdiv_lds_bytes(int rbytes) { return (size_t)12
 // solves launch both the CT = float kernel and the CT = double one; the
 // control block's rs64 flag selects which of the two does the work (the
 // FP64 one once the FP32 residual has stalled at its rounding floor).
-template <typename R, int PL, typename CT = R>
-__global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4) k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
-  const int2 w = work[blockIdx.x];
+template <typename R, int PL, typename CT, int TR>
+__device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const int2 w) {
   const SolveDev& s = S[w.x];
   const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
   if (C->status != ST_RUNNING) return;
@@ -491,7 +493,7 @@ __global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4) k_sdiv(const Sol
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k] = 0;
-  const NodeXY<CT> nxy = node_xy<CT>(s, C, J0, J1);
+  const NodeXY<CT> nxy = node_xy<CT>(s, J0, J1);
   // plastic solves read the stresses of the per-voxel stress pass
   const bool from_buf = PL && s.sig != nullptr;
   // FP32 corner carry: top corner 4 (FP64) and corners 5-7 minus it, per component
@@ -595,15 +597,15 @@ __global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4) k_sdiv(const Sol
     }
     if (zl >= Z0) {
       column_partials<CT>(s, sprev, scur, zl, sl + threadIdx.x);
-      CT fz[3], tz[3];
+      CT fz[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const bool face = s.kinds[q][2] != K_DFT && (zl == 0 || zl == n2);
         fz[q] = node_kept(s.kinds[q][2], n2, zl) ? (face ? (CT)2 : (CT)1) : (CT)0;
-        tz[q] = !C->has_trac ? (CT)0 : zl == 0 ? dstar<CT>(C, 2, 0, q) : zl == n2 ? dstar<CT>(C, 2, 1, q) : (CT)0;
       }
       __syncthreads();
-      if (has_node) node_div<CT, R>(sl, lx, ly, nxy, fz, tz, Dcol + (int64_t)zl * N01, s.Nn, acc[7]);
+      if (has_node)
+        node_div<CT, R, TR>(sl, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx, Y0 + ly, zl);
       __syncthreads();
     }
 #pragma unroll
@@ -619,6 +621,25 @@ __global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4) k_sdiv(const Sol
   block_sum<8>(accd, outp);
   __syncthreads();
   if (threadIdx.x < 8) gmut(s.part_s)[(int64_t)w.y * NPART_S + threadIdx.x] = outp[threadIdx.x];
+}
+
+// The FP64 variant of an FP32 group is launched every iteration but works
+// only for solves near their FP32 rounding floor: it runs as a few blocks
+// per compute unit walking the tile list, so that it costs a short dispatch
+// when no solve needs it.
+// TR = 1 adds the applied-traction term D* at the loaded faces (groups whose
+// load paths carry tractions; the common kernel carries no traction code).
+template <typename R, int PL, typename CT = R, int TR = 0>
+__global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4)
+    k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work, int nwork) {
+  if constexpr (sizeof(R) == 4 && sizeof(CT) == 8) {
+    for (int i = blockIdx.x; i < nwork; i += gridDim.x) {
+      sdiv_tile<R, PL, CT, TR>(S, work[i]);
+      __syncthreads();
+    }
+  } else {
+    sdiv_tile<R, PL, CT, TR>(S, work[blockIdx.x]);
+  }
 }
 
 // Gram matrix of the residual window, on Anderson steps only.  Dismissed
