@@ -306,6 +306,24 @@ int fm_server_poll(fm_server* s, uint64_t ticket, int32_t* state, double* latenc
 int fm_server_stats(fm_server* s, fm_stats* out);
 void fm_server_destroy(fm_server* s);
 
+/* ---- Allocation-free solve ---------------------------------------------
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid it): fm_solve_static does what fm_plan_create +
+ * fm_set_material + fm_solve + fm_plan_destroy do, with the plan's workspace
+ * taken from a device array inside the library (FM_STATIC_SCRATCH_BYTES per
+ * GPU, held by each GPU the library runs on until the process ends) instead
+ * of a caller buffer; iterations are launched directly (no captured graphs).
+ * The caller passes the inputs (d_mat_id: device, int32 per voxel; table and
+ * steps: host) and the outputs as for fm_solve.  Returns FM_E_CAPACITY when
+ * fm_workspace_bytes(desc) exceeds FM_STATIC_SCRATCH_BYTES, otherwise what
+ * fm_solve returns.  Every call on one GPU uses that GPU's one array: calls
+ * that overlap on a GPU (two threads or two streams) race; the array keeps
+ * the last call's contents, and each call initialises what it reads. */
+#define FM_STATIC_SCRATCH_BYTES (64u << 20)
+int fm_solve_static(const fm_plan_desc* desc, const int32_t* d_mat_id, int32_t n_mat, const fm_material* table,
+                    const fm_load_step* steps, int32_t n_steps, fm_outputs* out, fm_iter_log* log,
+                    void* hip_stream);
+
 const char* fm_last_error(void);
 
 #ifdef __cplusplus

@@ -101,6 +101,9 @@ EXPORTS = {
     "fm_server_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "fm_server_destroy": (None, [C.c_void_p]),
     "fm_last_error": (C.c_char_p, []),
+    "fm_solve_static": (C.c_int, [C.POINTER(PlanDesc), C.c_void_p, C.c_int32, C.POINTER(Material),
+                                  C.POINTER(LoadStep), C.c_int32, C.POINTER(Outputs), C.POINTER(IterLog),
+                                  C.c_void_p]),
     "fm_set_graph_launch": (C.c_int, [C.c_int]),
     "fm_autotune": (C.c_int, [C.c_void_p, C.POINTER(LoadStep), C.c_int32, C.POINTER(C.c_int32),
                               C.POINTER(C.c_double)]),
@@ -352,6 +355,39 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def solve_static(prob, prec=None):
+    """fm_solve_static: one solve on the library's static device scratch (the
+    library allocates nothing); outputs as Plan.solve."""
+    torch = _torch()
+    d = plan_desc(prob, prec)
+    ids = torch.as_tensor(np.ascontiguousarray(prob.mat_id, dtype=np.int32).reshape(-1), device="cuda")
+    tab = material_table(prob)
+    st = load_steps(prob.steps)
+    ns = len(prob.steps)
+    n1, n2, n3 = (int(v) for v in prob.n)
+    nppv = 2 if prob.scheme == 1 else 1
+    nn = (n1 + 1) * (n2 + 1) * (n3 + 1)
+    nv = n1 * n2 * n3
+    bufs = {"u": torch.empty(3 * nn, dtype=torch.float64, device="cuda"),
+            "eps": torch.empty(6 * nppv * nv, dtype=torch.float64, device="cuda"),
+            "sig": torch.empty(6 * nppv * nv, dtype=torch.float64, device="cuda")}
+    macro = np.zeros((ns, 6))
+    iters = np.zeros(ns, dtype=np.int32)
+    conv = np.zeros(ns, dtype=np.int32)
+    out = Outputs()
+    out.u = bufs["u"].data_ptr(); out.eps = bufs["eps"].data_ptr(); out.sig = bufs["sig"].data_ptr()
+    out.macro_sigma = macro.ctypes.data_as(C.POINTER(C.c_double))
+    out.iters = iters.ctypes.data_as(C.POINTER(C.c_int32))
+    out.converged = conv.ctypes.data_as(C.POINTER(C.c_int32))
+    rc = check(lib().fm_solve_static(C.byref(d), C.c_void_p(ids.data_ptr()), len(prob.materials), tab, st, ns,
+                                     C.byref(out), None, _stream_ptr(torch)), "fm_solve_static")
+    torch.cuda.current_stream().synchronize()
+    return {"rc": rc, "macro_sigma": macro, "iters": iters.tolist(), "converged": [bool(v) for v in conv],
+            "u": bufs["u"].cpu().numpy().reshape(3, n3 + 1, n2 + 1, n1 + 1),
+            "eps": bufs["eps"].cpu().numpy().reshape(6, nppv, n3, n2, n1),
+            "sig": bufs["sig"].cpu().numpy().reshape(6, nppv, n3, n2, n1)}
 
 
 def set_graph_launch(enable: bool):

@@ -477,6 +477,7 @@ struct Group {
   int prec = 0;
   int plastic = 0;    // any solve with J2 / CP internal variables
   int trac = 0;       // some load path of the group applies tractions (real-space kernel with D*)
+  bool eager = false; // launch directly, never through captured graphs
   int ns = 0;
   hipStream_t stream = nullptr;
   SolveDev* S = nullptr;
@@ -1218,7 +1219,7 @@ int capture_chunk(Group& G, int idx) {
 // Enqueue `count` iterations: as a sum of captured power-of-two chunks, or
 // eagerly (nine launches each) when graphs are switched off.
 int launch_iterations(Group& G, int count) {
-  if (!g_use_graphs) return launch_iterations_eager(G, count);
+  if (!g_use_graphs || G.eager) return launch_iterations_eager(G, count);
   while (count > 0) {
     int idx = 0;
     while (idx + 1 < Group::NGRAPH && (2 << idx) <= count) ++idx;
@@ -1827,3 +1828,58 @@ int fm_autotune(fm_plan* p, const fm_load_step* step, int32_t n_iter, int32_t* c
 }  // extern "C"
 
 #include "fm_batch.inc"
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve (callers that cannot allocate device memory)
+// ---------------------------------------------------------------------------
+// The workspace of fm_solve_static is this file-scope device array.  In host
+// code its name is only a stand-in: the device address of each GPU's copy is
+// taken once per device with hipGetSymbolAddress and used everywhere after.
+static __device__ __align__(256) char scratch[FM_STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;   // device index -> address of that device's scratch
+
+int scratch_address(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, (char*)ptr).first;
+  }
+  *out = it->second;
+  return 0;
+}
+}  // namespace
+
+extern "C" {
+
+int fm_solve_static(const fm_plan_desc* desc, const int32_t* d_mat_id, int32_t n_mat, const fm_material* table,
+                    const fm_load_step* steps, int32_t n_steps, fm_outputs* out, fm_iter_log* log,
+                    void* hip_stream) {
+  if (!desc || !d_mat_id || !table || !steps || n_steps < 1) return fail(FM_E_INVALID_ARG, "null argument");
+  const size_t need = fm_workspace_bytes(desc);
+  if (!need) return FM_E_INVALID_ARG;
+  if (need > (size_t)FM_STATIC_SCRATCH_BYTES)
+    return fail(FM_E_CAPACITY, "workspace of " + std::to_string(need) + " bytes exceeds the static scratch of " +
+                                   std::to_string((size_t)FM_STATIC_SCRATCH_BYTES) + " bytes");
+  char* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  fm_plan* p = nullptr;
+  rc = fm_plan_create(desc, ws, FM_STATIC_SCRATCH_BYTES, hip_stream, &p);
+  if (rc) return rc;
+  p->self->eager = true;
+  rc = fm_set_material(p, d_mat_id, n_mat, table);
+  if (rc == 0) rc = fm_solve(p, steps, n_steps, out, log);
+  fm_plan_destroy(p);
+  return rc;
+}
+
+}  // extern "C"
