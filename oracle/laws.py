@@ -21,7 +21,7 @@ import itertools
 
 import numpy as np
 
-LAW_ISO, LAW_ANISO, LAW_J2, LAW_CP = 0, 1, 2, 3
+LAW_ISO, LAW_ANISO, LAW_J2, LAW_CP, LAW_SVK, LAW_NEOHOOKE = 0, 1, 2, 3, 4, 5
 SQ2 = np.sqrt(2.0)
 _MANDEL_IJ = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
 
@@ -191,6 +191,30 @@ def j2_update(eps, epn, pn, lam, mu, sy0, H):
     return sig_new, ep, pn + dp
 
 
+# ---------------------------------------------------------------------------
+# Finite strain (Lagrangian formulation of Sec. 2.2): F = 1 + grad u,
+# E = (F^T F - 1) / 2, second Piola-Kirchhoff Pi = d psi / dE, first P = F Pi.
+# ---------------------------------------------------------------------------
+def svk_pk1(F, lam, mu):
+    """Saint Venant-Kirchhoff (Sec. 3.1.2): Pi = lam tr(E) 1 + 2 mu E (the
+    factor 2 on mu as for the small-strain law, reading R6); P = F Pi."""
+    E = 0.5 * (np.einsum("...ki,...kj->...ij", F, F) - np.eye(3))
+    tr = np.trace(E, axis1=-2, axis2=-1)
+    Pi = lam * tr[..., None, None] * np.eye(3) + 2.0 * mu * E
+    return F @ Pi
+
+
+def neohooke_pk1(F, mu, K):
+    """Compressible Neo-Hookean of Appendix B, psi = mu/2 (J^-2/3 tr(F F^T) - 3)
+    + K/2 (J - 1)^2, differentiated with respect to F:
+    P = mu J^-2/3 (F - tr(F F^T)/3 F^-T) + K (J - 1) J F^-T."""
+    J = np.linalg.det(F)
+    Finv_T = np.swapaxes(np.linalg.inv(F), -1, -2)
+    I1 = np.einsum("...ij,...ij->...", F, F)
+    return (mu * J[..., None, None] ** (-2.0 / 3.0) * (F - (I1 / 3.0)[..., None, None] * Finv_T)
+            + (K * (J - 1.0) * J)[..., None, None] * Finv_T)
+
+
 class MaterialSet:
     """Per-voxel material table for the oracle.
 
@@ -206,7 +230,10 @@ class MaterialSet:
         ms, ns = fcc_slip_systems()
         for m in materials:
             law = m["law"]
-            if law in (LAW_ISO, LAW_J2):
+            if law in (LAW_SVK, LAW_NEOHOOKE):
+                self.C.append(None)
+                self.P.append(None)
+            elif law in (LAW_ISO, LAW_J2):
                 self.C.append(iso_tensor(m["lam"], m["mu"]))
                 self.P.append(None)
             else:
@@ -220,6 +247,22 @@ class MaterialSet:
                 else:
                     self.P.append(None)
         self.masks = [mat_id == k for k in range(len(materials))]
+
+    def pk1(self, F):
+        """First Piola-Kirchhoff stress P[..., q, J] of the hyperelastic laws
+        for the deformation gradient F[..., q, J] at the points (finite strain)."""
+        P = np.zeros_like(F)
+        for k, m in enumerate(self.materials):
+            mk = self.masks[k]
+            if not mk.any():
+                continue
+            if m["law"] == LAW_SVK:
+                P[:, mk] = svk_pk1(F[:, mk], m["lam"], m["mu"])
+            elif m["law"] == LAW_NEOHOOKE:
+                P[:, mk] = neohooke_pk1(F[:, mk], m["mu"], m["K"])
+            else:
+                raise ValueError("finite-strain solves take the SVK and Neo-Hookean laws")
+        return P
 
     def has_state(self) -> bool:
         return any(m["law"] in (LAW_J2, LAW_CP) for m in self.materials)

@@ -169,6 +169,7 @@ def solve(prob, callback=None):
     nvox = n[0] * n[1] * n[2]
     log, macro, iters, conv, Gs = [], [], [], [], []
     C0 = c0_voigt(pl.lam0, pl.mu0)
+    fs = bool(getattr(prob, "finite_strain", 0))
     for t, step in enumerate(prob.steps):
         G = np.array(step.G, dtype=np.float64).copy()
         if t > 0 and np.any(step.mixed_mask) and len(Gs):
@@ -185,12 +186,23 @@ def solve(prob, callback=None):
         m = 0
         while True:
             us = pl.ustar(step.c, G, step.H)
-            gu = pl.grad(uf) + pl.grad(us)
-            eps = 0.5 * (gu + np.swapaxes(gu, -1, -2))
-            sig, trial = mats.stress(eps, state, step.dt)
+            gu = pl.grad(uf) + pl.grad(us)            # gu[..., l, q] = D_l u_q
+            if fs:
+                # Lagrangian finite strain (Sec. 2.2): F[q, J] = delta + D_J u_q,
+                # P = F Pi; the divergence contracts the derivative index of
+                # S[l, q] = P[q, l], column-wise mirror rules as for sigma
+                F = np.eye(3) + np.swapaxes(gu, -1, -2)
+                P = mats.pk1(F)
+                sig = np.swapaxes(P, -1, -2)
+                trial = state
+            else:
+                eps = 0.5 * (gu + np.swapaxes(gu, -1, -2))
+                sig, trial = mats.stress(eps, state, step.dt)
             Dv = pl.div(sig) + Dstar
             err = equilibrium_error(pl, Dv, sig)
             ms = sig.mean(axis=(0, 1, 2, 3))
+            if fs:
+                ms = ms.T                                # <P>[q, J]
             mvo = np.array([ms[i, j] for (i, j) in VOIGT])
             mixed_ok = True
             if S_idx.size:
@@ -239,6 +251,12 @@ def solve(prob, callback=None):
         conv.append(converged)
     us = pl.ustar(prob.steps[-1].c, Gs[-1], prob.steps[-1].H)
     u = uf + us
+    if fs:
+        # outputs of a finite-strain solve: Green-Lagrange strain and Cauchy stress
+        F = np.eye(3) + np.swapaxes(gu, -1, -2)
+        P = np.swapaxes(sig, -1, -2)
+        eps = 0.5 * (np.einsum("...ki,...kj->...ij", F, F) - np.eye(3))
+        sig = (P @ np.swapaxes(F, -1, -2)) / np.linalg.det(F)[..., None, None]
 
     def vox_out(T):
         out = np.empty((6, pl.nppv, n[2], n[1], n[0]))

@@ -389,3 +389,51 @@ def test_c0_rejects_non_normal_mixed():
     prob.green = W.GREEN_C0
     with pytest.raises(ValueError):
         Plan(prob)
+
+
+def _fe_force_of_field(S, n, h, scheme, per):
+    """FE nodal force f_a,q = sum_e w_e sum_l B_a,l S_lq of a given per-point
+    tensor field S[r, x, y, z, l, q] (not necessarily symmetric)."""
+    N = tuple(v + 1 for v in n)
+    f = np.zeros((3,) + N)
+    corners = list(itertools.product((0, 1), repeat=3))
+    if scheme == 0:
+        sets = [(0, corners, np.array([[(2 * a[i] - 1) / (4.0 * h) for i in range(3)] for a in corners]), 1.0)]
+    else:
+        even = [c for c in corners if sum(c) % 2 == 0]
+        odd = [c for c in corners if sum(c) % 2 == 1]
+        sets = [(r, tet, _tet_grads(np.array(tet, dtype=float) * h), 0.5) for r, tet in enumerate((even, odd))]
+    for j1, j2, j3 in itertools.product(range(n[0]), range(n[1]), range(n[2])):
+        for r, nodes, B, wt in sets:
+            Sv = S[r, j1, j2, j3]
+            for a, b in zip(nodes, B):
+                f[:, j1 + a[0], j2 + a[1], j3 + a[2]] += wt * h ** 3 * (Sv.T @ b)
+    perm = np.broadcast_to(np.asarray(per, dtype=bool), (3, 3))
+    for q in range(3):
+        for i in range(3):
+            if perm[q, i]:
+                s0 = [q, slice(None), slice(None), slice(None)]; s0[i + 1] = 0
+                sn = [q, slice(None), slice(None), slice(None)]; sn[i + 1] = -1
+                f[tuple(s0)] += f[tuple(sn)]
+                f[tuple(sn)] = f[tuple(s0)]
+    return f
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("seed", range(3))
+def test_divergence_of_nonsymmetric_field_equals_fe_assembly(scheme, seed):
+    """P6 for the finite-strain divergence: a random non-symmetric per-point
+    field (first Piola-Kirchhoff stresses are not symmetric), every Table 1
+    pair per component and axis; the column-wise mirror rules make the
+    divergence equal the FE nodal force (times 2 per symmetric face)."""
+    rng = np.random.default_rng(1300 + seed)
+    n = (3, 4, 3)
+    h = 0.8
+    ext3 = [[PAIRS[int(rng.integers(0, 5))] for i in range(3)] for q in range(3)]
+    S = rng.standard_normal((fd.n_ppv(scheme),) + n + (3, 3))
+    D = fd.divergence(S, ext3, scheme, h)
+    per = [[ext3[q][i][0] == "P" for i in range(3)] for q in range(3)]
+    f = _fe_force_of_field(S, n, h, scheme, per)
+    for q in range(3):
+        keep = fd.kept_mask(ext3[q], n)
+        np.testing.assert_allclose(D[q][keep], (-f[q] / h ** 3 * _face_weight(ext3[q], n))[keep], atol=1e-12)

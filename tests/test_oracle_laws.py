@@ -223,3 +223,40 @@ def test_frame_equivariance(law):
         eps_r = eps_r * 1.5; eps_i = eps_i * 1.5
     if law == "cp":
         assert ni["p"][0, 0, 0, 0] > 0                 # slip happened
+
+
+def _fd_pk1(psi, F, h=1e-6):
+    """P = d psi / dF by central differences of the strain energy."""
+    P = np.zeros((3, 3))
+    for i in range(3):
+        for j in range(3):
+            Fp = F.copy(); Fp[i, j] += h
+            Fm = F.copy(); Fm[i, j] -= h
+            P[i, j] = (psi(Fp) - psi(Fm)) / (2 * h)
+    return P
+
+
+def test_finite_strain_laws_derive_from_their_energies():
+    """P of the SVK and Neo-Hookean laws = d psi / dF of the energies written
+    out here (SVK: lam/2 tr(E)^2 + mu tr(E^2); Neo-Hookean, Appendix B:
+    mu/2 (J^-2/3 tr(F F^T) - 3) + K/2 (J - 1)^2), at random deformations."""
+    rng = np.random.default_rng(12)
+    lam, mu, K = 1.2, 0.8, 2.5
+
+    def psi_svk(F):
+        E = 0.5 * (F.T @ F - np.eye(3))
+        return 0.5 * lam * np.trace(E) ** 2 + mu * np.trace(E @ E)
+
+    def psi_nh(F):
+        J = np.linalg.det(F)
+        return 0.5 * mu * (J ** (-2.0 / 3.0) * np.trace(F @ F.T) - 3.0) + 0.5 * K * (J - 1.0) ** 2
+
+    for _ in range(5):
+        F = np.eye(3) + 0.2 * rng.standard_normal((3, 3))
+        np.testing.assert_allclose(laws.svk_pk1(F, lam, mu), _fd_pk1(psi_svk, F), atol=1e-7)
+        np.testing.assert_allclose(laws.neohooke_pk1(F, mu, K), _fd_pk1(psi_nh, F), atol=1e-7)
+    # objectivity: P(Q F) = Q P(F) for a rotation Q
+    Q = laws.quat_to_rot(rng.standard_normal(4))
+    F = np.eye(3) + 0.2 * rng.standard_normal((3, 3))
+    np.testing.assert_allclose(laws.neohooke_pk1(Q @ F, mu, K), Q @ laws.neohooke_pk1(F, mu, K), atol=1e-12)
+    np.testing.assert_allclose(laws.svk_pk1(Q @ F, lam, mu), Q @ laws.svk_pk1(F, lam, mu), atol=1e-12)

@@ -258,3 +258,77 @@ def test_c0_fixed_point_equals_b0(scheme, seed):
     eps_d, sig_d, res = _direct_solve(prob)
     ref = np.stack([sig_d[..., i, j] for (i, j) in solver.VOIGT]).transpose(0, 1, 4, 3, 2)
     np.testing.assert_allclose(rc["sig"], ref, atol=1e-8 * scale)
+
+
+def _nh_tension_closed_form(e, mu, K):
+    """Appendix B: homogeneous tension F = diag(e, t, t) of the compressible
+    Neo-Hookean bar.  P22(t) = mu/3 e t (e t^2)^-5/3 (t^2 - e^2) + K e t
+    (e t^2 - 1) (from the energy; the printed P22 has (t^2 - 1) in its
+    volumetric term, which drops J = e t^2) vanishes on the free lateral faces;
+    t by bisection, then P11 = 2/3 mu t^2 (e t^2)^-5/3 (e^2 - t^2) + K (e t^4 - t^2)."""
+    def P22(t):
+        return mu / 3.0 * e * t * (e * t * t) ** (-5.0 / 3.0) * (t * t - e * e) + K * e * t * (e * t * t - 1.0)
+    lo, hi = 0.3, 1.0 + 1e-12
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if P22(lo) * P22(mid) <= 0:
+            hi = mid
+        else:
+            lo = mid
+    t = 0.5 * (lo + hi)
+    P11 = 2.0 / 3.0 * mu * t * t * (e * t * t) ** (-5.0 / 3.0) * (e * e - t * t) + K * (e * t ** 4 - t * t)
+    return t, P11
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+def test_neohooke_pure_tension_closed_form(scheme):
+    """Appendix B: a Neo-Hookean bar stretched by Dirichlet conditions on u_x
+    of its x faces (every other face and component free) is homogeneously
+    stretched; <P11> follows the semi-analytic law over large elongations and
+    the lateral stress vanishes."""
+    n = (6, 3, 3)
+    mu, K = 0.8, 2.0
+    bc = np.full((3, 3, 2), W.N, dtype=np.int32)
+    bc[0, 0, :] = W.D
+    es = [1.05, 1.15, 1.3]
+    steps = []
+    for e in es:
+        s = W.LoadStep(); s.G[0, 0] = e - 1.0
+        steps.append(s)
+    prob = W.Problem(n=n, h=1.0, bc=bc, scheme=scheme, green=W.GREEN_B0, lambda0=K, mu0=mu,
+                     materials=[W.mat_neohooke(mu, K)], mat_id=np.zeros((n[2], n[1], n[0]), dtype=np.int32),
+                     steps=steps, tol=1e-12, max_iter=3000, finite_strain=1)
+    r = solver.solve(prob)
+    assert all(r["converged"])
+    for k, e in enumerate(es):
+        t, P11 = _nh_tension_closed_form(e, mu, K)
+        assert r["macro_sigma"][k][0] == pytest.approx(P11, rel=1e-9)
+        assert abs(r["macro_sigma"][k][1]) < 1e-10 and abs(r["macro_sigma"][k][2]) < 1e-10
+    # the lateral contraction of the last increment
+    t, _ = _nh_tension_closed_form(es[-1], mu, K)
+    Exx, Eyy = r["eps"][0].mean(), r["eps"][1].mean()
+    assert Eyy == pytest.approx(0.5 * (t * t - 1.0), rel=1e-9)
+    assert Exx == pytest.approx(0.5 * (es[-1] ** 2 - 1.0), rel=1e-9)
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+def test_finite_strain_small_load_limit(scheme):
+    """At small loads the finite-strain SVK solve of a random two-phase
+    problem reduces to the small-strain isotropic one: <P> - <sigma> is of
+    the order of the strain squared."""
+    rng = np.random.default_rng(31 + scheme)
+    small = W.random_small_problem(rng, n=(5, 4, 6), scheme=scheme, tol=1e-12)
+    for s in small.steps:
+        s.G *= 1e-3
+        s.H *= 1e-3
+    fs = W.random_small_problem(np.random.default_rng(31 + scheme), n=(5, 4, 6), scheme=scheme, tol=1e-12)
+    for s in fs.steps:
+        s.G *= 1e-3
+        s.H *= 1e-3
+    fs.materials = [W.mat_svk(m["lam"], m["mu"]) for m in fs.materials]
+    fs.finite_strain = 1
+    a = solver.solve(small)["macro_sigma"][0]
+    b = solver.solve(fs)["macro_sigma"][0]
+    scale = np.abs(a).max()
+    assert np.abs(a - b).max() < 1e-4 * scale
+    assert np.abs(a - b).max() > 0

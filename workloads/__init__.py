@@ -37,7 +37,7 @@ HEX1, TETRA2 = 0, 1
 GREEN_B0, GREEN_2MU0, GREEN_C0 = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 
-LAW_ISO, LAW_ANISO, LAW_J2, LAW_CP = 0, 1, 2, 3
+LAW_ISO, LAW_ANISO, LAW_J2, LAW_CP, LAW_SVK, LAW_NEOHOOKE = 0, 1, 2, 3, 4, 5
 
 
 # --------------------------------------------------------------------------
@@ -74,6 +74,16 @@ def mat_cp(C11, C12, C44, quat, gdot0, nexp, tau0, taus, theta0) -> dict:
             "quat": [float(v) for v in quat], "gdot0": float(gdot0),
             "n": float(nexp), "tau0": float(tau0), "taus": float(taus),
             "theta0": float(theta0)}
+
+
+def mat_svk(lam: float, mu: float) -> dict:
+    """Finite-strain Saint Venant-Kirchhoff, Pi = lam tr(E) 1 + 2 mu E."""
+    return {"law": LAW_SVK, "lam": float(lam), "mu": float(mu)}
+
+
+def mat_neohooke(mu: float, K: float) -> dict:
+    """Finite-strain compressible Neo-Hookean, psi = mu/2 (I1bar - 3) + K/2 (J - 1)^2."""
+    return {"law": LAW_NEOHOOKE, "mu": float(mu), "K": float(K)}
 
 
 # --------------------------------------------------------------------------
@@ -137,6 +147,7 @@ class Problem:
     aa_period: int = 3
     prec: int = FP64
     name: str = ""
+    finite_strain: int = 0       # 1: Lagrangian finite-strain formulation (P = F Pi)
 
     @property
     def n_vox(self) -> int:
