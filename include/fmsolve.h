@@ -90,6 +90,11 @@ extern "C" {
                            FCC 12 {111}<110> systems, gdot = gdot0 |tau/tc|^n sign(tau),
                            tc = tau0 + (taus-tau0)(1-exp(-theta0 Gamma/(taus-tau0))),
                            backward Euler */
+/* Hyperelastic laws of the finite-strain formulation (finite_strain = 1):
+ * first Piola-Kirchhoff P = F Pi, F = 1 + grad u, E = (F^T F - 1)/2. */
+#define FM_LAW_SVK      4  /* p = {lambda, mu}: Pi = lambda tr(E) 1 + 2 mu E (Sec. 3.1.2) */
+#define FM_LAW_NEOHOOKE 5  /* p = {mu, K}: psi = mu/2 (J^-2/3 tr(F F^T) - 3) + K/2 (J - 1)^2
+                              (Appendix B) */
 
 typedef struct {
   int32_t n[3];            /* voxels along x, y, z (each >= 2) */
@@ -108,6 +113,12 @@ typedef struct {
   int32_t aa_period;       /* Anderson applied when m >= 2 and m % period == 0 */
   int32_t max_materials;   /* capacity of the material table */
   int32_t with_state;      /* 1 if any material is J2 or CP (internal variables) */
+  int32_t finite_strain;   /* 1: Lagrangian finite strain (Sec. 2.2): the equilibrium of the
+                              first Piola-Kirchhoff stress, FM_LAW_SVK / FM_LAW_NEOHOOKE
+                              materials only; macro_sigma then holds <P> (P_11, P_22, P_33,
+                              P_23, P_13, P_12), eps the Green-Lagrange strain and sig the
+                              Cauchy stress, mixed_mask controls those <P> entries.  The C0
+                              operator takes its finite-strain form (Eq. FourierSGO). */
 } fm_plan_desc;
 
 typedef struct {

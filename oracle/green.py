@@ -130,15 +130,19 @@ def _extend3(g, kinds, n):
     return E * maps[0][1][:, None, None] * maps[1][1][None, :, None] * maps[2][1][None, None, :]
 
 
-def c0_apply(p, kinds, n, scheme: int, h: float, lam0: float, mu0: float) -> np.ndarray:
-    """u^f = DGO(p) of the C0 reference medium (small strain, Appendix A) on
+def c0_apply(p, kinds, n, scheme: int, h: float, lam0: float, mu0: float, finite: bool = False) -> np.ndarray:
+    """u^f = DGO(p) of the C0 reference medium on
     the virtually extended periodic fields: every component of p (node
     field, shape (3, n1+1, n2+1, n3+1)) is extended with its own symmetries
     (identical periods along each axis under Eq. SGO_BCs), transformed by a
     plain 3D DFT, mapped to u^f by the formulas of Appendix A with the
     modified frequencies of the scheme (HEX1: Eq. modified_freq_hex1; TETRA2:
     xi_T2 of Eq. freq_TETRA2), transformed back and restricted to the nodes.
-    Null modes (|xi| = 0, decided in index space) give 0."""
+    Small strain (C0 on the symmetric gradient): the formulas of Appendix A;
+    finite strain (C0 on the gradient): Eqs. FourierSGO_HEX1 and
+    FourierSGO_TETRA2_1/_2, i.e. the same with mu0 -> 2 mu0 in the leading
+    factor and mu0 + lambda0 -> lambda0 in the coupling.  Null modes (|xi| =
+    0, decided in index space) give 0."""
     if not c0_compatible(kinds):
         raise ValueError("the C0 operator needs normal-mixed boundary conditions (Eq. SGO_BCs)")
     Ps = [np.fft.fftn(_extend3(p[q], kinds[q], n)) for q in range(3)]
@@ -168,9 +172,10 @@ def c0_apply(p, kinds, n, scheme: int, h: float, lam0: float, mu0: float) -> np.
         ok = ~null
         xi2 = re[0] ** 2 + re[1] ** 2 + re[2] ** 2
         pd = Ps[0] * re[0] + Ps[1] * re[1] + Ps[2] * re[2]
-        k = (mu0 + lam0) / (2.0 * mu0 + lam0)
+        lead = 2.0 * mu0 if finite else mu0
+        k = (lam0 if finite else mu0 + lam0) / (2.0 * mu0 + lam0)
         for q in range(3):
-            U[q][ok] = -(Ps[q][ok] - k * pd[ok] * re[q][ok] / xi2[ok]) / (mu0 * xi2[ok])
+            U[q][ok] = -(Ps[q][ok] - k * pd[ok] * re[q][ok] / xi2[ok]) / (lead * xi2[ok])
     else:
         null = allz | (npi == 3)
         ok = ~null
@@ -180,8 +185,9 @@ def c0_apply(p, kinds, n, scheme: int, h: float, lam0: float, mu0: float) -> np.
         xi2 = sum(np.abs(v) ** 2 for v in xi)
         zz = xi[0] ** 2 + xi[1] ** 2 + xi[2] ** 2             # xi . xi
         zzb = np.conj(zz)
-        ca = 0.5 * (3.0 * mu0 + lam0) * xi2
-        cb = 0.5 * (mu0 + lam0)
+        lead = 2.0 * mu0 if finite else mu0
+        cb = 0.5 * (lam0 if finite else mu0 + lam0)
+        ca = (lead + cb) * xi2
         Ds = ca ** 2 - (cb * np.abs(zz)) ** 2
         px = Ps[0] * xi[0] + Ps[1] * xi[1] + Ps[2] * xi[2]    # p . xi
         pxb = Ps[0] * xib[0] + Ps[1] * xib[1] + Ps[2] * xib[2]
@@ -189,7 +195,7 @@ def c0_apply(p, kinds, n, scheme: int, h: float, lam0: float, mu0: float) -> np.
             p1 = (-ca * px + cb * zz * pxb) / Ds
             p2 = (cb * zzb * px - ca * pxb) / Ds
         for q in range(3):
-            U[q][ok] = -(Ps[q][ok] + cb * (p1[ok] * xib[q][ok] + p2[ok] * xi[q][ok])) / (mu0 * xi2[ok])
+            U[q][ok] = -(Ps[q][ok] + cb * (p1[ok] * xib[q][ok] + p2[ok] * xi[q][ok])) / (lead * xi2[ok])
     out = np.zeros_like(p)
     for q in range(3):
         e = np.fft.ifftn(U[q]).real

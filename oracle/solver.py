@@ -52,6 +52,7 @@ class Plan:
         self.lam0 = float(prob.lambda0)
         self.mu0 = float(prob.mu0)
         self.green = int(prob.green)
+        self.fs = bool(getattr(prob, "finite_strain", 0))
         bc = np.asarray(prob.bc)
         self.exts = [[(_dt.ext_of_bc(bc[q, i, 0]), _dt.ext_of_bc(bc[q, i, 1])) for i in range(3)]
                      for q in range(3)]
@@ -95,7 +96,10 @@ class Plan:
         g = self.grad(u)
         if self.green == 2:
             tr = np.trace(g, axis1=-2, axis2=-1)
-            tau0 = self.mu0 * (g + np.swapaxes(g, -1, -2)) + self.lam0 * tr[..., None, None] * np.eye(3)
+            if self.fs:          # finite strain: C0 on the gradient (Eq. TF_C0_behavior)
+                tau0 = 2.0 * self.mu0 * g + self.lam0 * tr[..., None, None] * np.eye(3)
+            else:                # small strain: C0 on the symmetric gradient (Appendix A)
+                tau0 = self.mu0 * (g + np.swapaxes(g, -1, -2)) + self.lam0 * tr[..., None, None] * np.eye(3)
             return self.div(tau0)
         lam = self.lam0 if self.green == 0 else 0.0
         tau0 = g * (2.0 * self.mu0 + lam * np.eye(3))    # factor on entry (l, q)
@@ -103,7 +107,7 @@ class Plan:
 
     def green_apply(self, x):
         if self.green == 2:
-            u = _green.c0_apply(x, self.kinds, self.n, self.scheme, self.h, self.lam0, self.mu0)
+            u = _green.c0_apply(x, self.kinds, self.n, self.scheme, self.h, self.lam0, self.mu0, finite=self.fs)
             for q in range(3):
                 _fd.zero_dismissed(u[q], self.exts[q])
             return u

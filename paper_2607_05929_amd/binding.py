@@ -28,7 +28,7 @@ class PlanDesc(C.Structure):
                 ("scheme", C.c_int32), ("green", C.c_int32), ("lambda0", C.c_double),
                 ("mu0", C.c_double), ("prec", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("aa_depth", C.c_int32), ("aa_period", C.c_int32),
-                ("max_materials", C.c_int32), ("with_state", C.c_int32)]
+                ("max_materials", C.c_int32), ("with_state", C.c_int32), ("finite_strain", C.c_int32)]
 
 
 class Material(C.Structure):
@@ -158,6 +158,7 @@ def plan_desc(prob, prec=None) -> PlanDesc:
     d.aa_period = int(prob.aa_period)
     d.max_materials = max(1, len(prob.materials))
     d.with_state = int(any(m["law"] in (2, 3) for m in prob.materials))
+    d.finite_strain = int(getattr(prob, "finite_strain", 0))
     return d
 
 
@@ -172,6 +173,10 @@ def material_table(prob):
             vals = [m["C11"], m["C12"], m["C44"]]
         elif m["law"] == 2:
             vals = [m["lam"], m["mu"], m["sy0"], m["H"]]
+        elif m["law"] == 4:
+            vals = [m["lam"], m["mu"]]
+        elif m["law"] == 5:
+            vals = [m["mu"], m["K"]]
         else:
             vals = [m["C11"], m["C12"], m["C44"], m["gdot0"], m["n"], m["tau0"], m["taus"],
                     m["theta0"]]
@@ -410,7 +415,14 @@ def batch_solve(problems, prec=None, fields=False, plans=None):
     torch = _torch()
     own = plans is None
     if own:
-        plans = [Plan(p, prec) for p in problems]
+        plans = []
+        try:
+            for p in problems:
+                plans.append(Plan(p, prec))
+            return batch_solve(problems, prec, fields, plans)
+        finally:
+            for pl in plans:
+                pl.close()
     n = len(plans)
     handles = (C.c_void_p * n)(*[p.handle.value for p in plans])
     steps = [load_steps(p.steps) for p in problems]
@@ -441,9 +453,6 @@ def batch_solve(problems, prec=None, fields=False, plans=None):
             r["sig"] = bufs[i]["sig"].cpu().numpy().reshape(6, pl.nppv, n3, n2, n1)
             r["eps"] = bufs[i]["eps"].cpu().numpy().reshape(6, pl.nppv, n3, n2, n1)
         res.append(r)
-    if own:
-        for pl in plans:
-            pl.close()
     return res
 
 

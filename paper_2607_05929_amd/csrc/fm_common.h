@@ -129,6 +129,7 @@ struct SolveDev {
   // C0 Green operator (normal-mixed conditions only): the z pass is split
   // into a forward transform into per-component z-spectral buffers, the
   // coupled per-frequency apply, and the inverse transform
+  int32_t fs;              // 1: finite-strain formulation (sig holds P^T, 9 per point)
   int32_t c0;              // 1 if the plan uses the C0 operator
   int32_t c0_cplx;         // z-spectral coefficients are complex (some axis periodic)
   int32_t c0_U[3];         // frequencies per axis, shared by the components

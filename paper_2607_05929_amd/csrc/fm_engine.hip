@@ -27,6 +27,7 @@
 #include "fm_space.h"
 #include "fm_wave.h"
 #include "fm_green_c0.h"
+#include "fm_finite.h"
 
 using namespace fm;
 
@@ -138,6 +139,8 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   if (d->aa_period < 1) return fail(FM_E_INVALID_ARG, "aa_period must be >= 1");
   if (d->max_iter < 1) return fail(FM_E_INVALID_ARG, "max_iter must be >= 1");
   if (d->max_materials < 1 || d->max_materials > 65535) return fail(FM_E_INVALID_ARG, "max_materials must be in 1..65535");
+  if (d->finite_strain != 0 && d->finite_strain != 1) return fail(FM_E_INVALID_ARG, "finite_strain must be 0 or 1");
+  if (d->finite_strain && d->with_state) return fail(FM_E_UNSUPPORTED, "finite-strain plans take hyperelastic laws only");
   for (int q = 0; q < 3; ++q)
     for (int i = 0; i < 3; ++i) {
       for (int a = 0; a < 2; ++a)
@@ -313,7 +316,9 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
   L.mlaw = take(4 * (size_t)d->max_materials);
   L.mtab = take(R * MT_STRIDE * (size_t)d->max_materials);
   L.state = d->with_state ? take(R * 7 * g.nppv * (size_t)g.Nv) : 0;
-  L.sig = d->with_state ? take(R * 6 * g.nppv * (size_t)g.Nv) : 0;
+  // plastic plans: sigma of the iterate (6 per point); finite strain: P^T (9 per point)
+  L.sig = d->finite_strain ? take(sizeof(double) * 9 * g.nppv * (size_t)g.Nv)
+          : d->with_state   ? take(R * 6 * g.nppv * (size_t)g.Nv) : 0;
   L.part_s = take(8 * NPART_S * (size_t)g.ntile_s);
   L.part_d = take(8 * (size_t)g.ntile_d);
   L.part_g = take(8 * NGRAM * (size_t)g.ntile_d);
@@ -409,6 +414,14 @@ int material_entry(const fm_material& mt, double* e /* MT_STRIDE */) {
       e[15] = mt.p[3]; e[16] = mt.p[4]; e[17] = mt.p[5]; e[18] = mt.p[6]; e[19] = mt.p[7];
       return LAW_CP;
     }
+    case FM_LAW_SVK:
+      if (!(mt.p[1] > 0) || !(mt.p[0] + 2.0 / 3.0 * mt.p[1] > 0)) return fail(FM_E_INVALID_ARG, "SVK needs mu > 0 and a positive bulk modulus");
+      e[0] = mt.p[0]; e[1] = mt.p[1];
+      return LAW_SVK;
+    case FM_LAW_NEOHOOKE:
+      if (!(mt.p[0] > 0) || !(mt.p[1] > 0)) return fail(FM_E_INVALID_ARG, "Neo-Hookean needs mu > 0 and K > 0");
+      e[0] = mt.p[0]; e[1] = mt.p[1];
+      return LAW_NEOHOOKE;
     default:
       return fail(FM_E_INVALID_ARG, "unknown law");
   }
@@ -478,6 +491,7 @@ struct Group {
   int plastic = 0;    // any solve with J2 / CP internal variables
   int trac = 0;       // some load path of the group applies tractions (real-space kernel with D*)
   bool eager = false; // launch directly, never through captured graphs
+  int fs = 0;         // finite-strain solves (one formulation per group)
   int ns = 0;
   hipStream_t stream = nullptr;
   SolveDev* S = nullptr;
@@ -748,6 +762,9 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   G.ns = ns;
   G.plastic = 0;
   for (int i = 0; i < ns; ++i) G.plastic |= plans[i]->d.with_state ? 1 : 0;
+  G.fs = plans[0]->d.finite_strain;
+  for (int i = 0; i < ns; ++i)
+    if (plans[i]->d.finite_strain != G.fs) return fail(FM_E_INVALID_ARG, "a batch must share one formulation (small or finite strain)");
   G.stream = stream;
   int64_t t[NWL] = {};
   for (int i = 0; i < ns; ++i) {
@@ -1124,6 +1141,15 @@ template <typename R, int TR>
 int launch_sdiv(const Group& G) {
   hipStream_t st = G.stream;
   const int nw = (int)G.nwl[WL_SDIV];
+  if (G.fs) {
+    // finite strain: P per voxel (FP64 law, R storage), then its divergence
+    if (G.nwl[WL_VOX])
+      hipLaunchKernelGGL((k_fs_stress<R>), dim3(G.nwl[WL_VOX] * (SPACE_TILE / 256)), dim3(256), 0, st, G.S,
+                         G.wl[WL_VOX]);
+    hipLaunchKernelGGL((k_fs_div<R>), dim3(nw), dim3(256), 0, st, G.S, G.wl[WL_SDIV]);
+    HIPCHK(hipGetLastError());
+    return 0;
+  }
   // FP32 groups launch the FP32 and the FP64 real-space kernel; each solve's
   // control block picks the one that works (the other returns)
   if (G.plastic) {
@@ -1236,7 +1262,8 @@ int launch_iterations(Group& G, int count) {
 template <typename R>
 int launch_commit_t(fm_plan* p) {
   const Group& G = *p->self;
-  if (G.plastic) hipLaunchKernelGGL((k_commit<R, 1>), dim3(G.nwl[WL_VOX]), dim3(256), 0, G.stream, G.S, G.wl[WL_VOX]);
+  if (G.fs) hipLaunchKernelGGL((k_fs_out<R>), dim3(G.nwl[WL_VOX]), dim3(256), 0, G.stream, G.S, G.wl[WL_VOX]);
+  else if (G.plastic) hipLaunchKernelGGL((k_commit<R, 1>), dim3(G.nwl[WL_VOX]), dim3(256), 0, G.stream, G.S, G.wl[WL_VOX]);
   else hipLaunchKernelGGL((k_commit<R, 0>), dim3(G.nwl[WL_VOX]), dim3(256), 0, G.stream, G.S, G.wl[WL_VOX]);
   HIPCHK(hipGetLastError());
   return 0;
@@ -1500,7 +1527,8 @@ int fm_plan_create(const fm_plan_desc* desc, void* d_workspace, size_t ws_bytes,
   s.mtab = ws + p->lay.mtab;
   s.mlaw = (const int32_t*)(ws + p->lay.mlaw);
   s.state = desc->with_state ? ws + p->lay.state : nullptr;
-  s.sig = desc->with_state ? ws + p->lay.sig : nullptr;
+  s.sig = (desc->with_state || desc->finite_strain) ? ws + p->lay.sig : nullptr;
+  s.fs = desc->finite_strain ? 1 : 0;
   s.ctrl = (Ctrl*)(ws + p->lay.ctrl);
   s.log = (LogEntry*)(ws + p->lay.log);
   s.part_s = (double*)(ws + p->lay.part_s);
@@ -1571,6 +1599,8 @@ int fm_set_material(fm_plan* p, const int32_t* d_mat_id, int32_t n_mat, const fm
     if (law < 0) return law;
     if ((law == LAW_J2 || law == LAW_CP) && !p->d.with_state)
       return fail(FM_E_UNSUPPORTED, "J2 / CP materials need with_state = 1 in the plan");
+    if ((law == LAW_SVK || law == LAW_NEOHOOKE) != (p->d.finite_strain != 0))
+      return fail(FM_E_UNSUPPORTED, "finite-strain plans take the SVK and Neo-Hookean laws, small-strain plans the others");
     laws[i] = law;
     for (int k = 0; k < MT_STRIDE; ++k) {
       if (R == 8) ((double*)tab.data())[(size_t)i * MT_STRIDE + k] = e[k];

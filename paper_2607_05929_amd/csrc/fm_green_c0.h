@@ -97,7 +97,9 @@ __global__ void __launch_bounds__(C0_TILE) k_green_c0(const SolveDev* __restrict
   }
   cx<R> u[3] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
   if (xi2 != (R)0) {
-    const R mu0 = (R)s.mu0, b = (R)(s.mu0 + s.lam0);
+    // small strain (Appendix A): K = mu0 |xi|^2 + (mu0 + lambda0) Re(xi xi^H);
+    // finite strain (Eq. FourierSGO): K = 2 mu0 |xi|^2 + lambda0 Re(xi xi^H)
+    const R mu0 = (R)(s.fs ? 2.0 * s.mu0 : s.mu0), b = (R)(s.fs ? s.lam0 : s.mu0 + s.lam0);
     R K[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)

@@ -17,7 +17,7 @@
 
 namespace fm {
 
-enum Law : int { LAW_ISO = 0, LAW_ANISO = 1, LAW_J2 = 2, LAW_CP = 3 };
+enum Law : int { LAW_ISO = 0, LAW_ANISO = 1, LAW_J2 = 2, LAW_CP = 3, LAW_SVK = 4, LAW_NEOHOOKE = 5 };
 
 template <typename R> struct LawTol;
 template <> struct LawTol<float> { static constexpr float cp = 2e-6f; };

@@ -346,10 +346,12 @@ def test_applied_traction_equals_fe_face_load(scheme, seed):
         np.testing.assert_allclose(D[q][keep], (-f[q] / h ** 3 * _face_weight(ext3[q], n))[keep], atol=1e-12)
 
 
+@pytest.mark.parametrize("finite", [False, True])
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_c0_green_inverts_L0(scheme):
+def test_c0_green_inverts_L0(scheme, finite):
     """P5 for the C0 operator (Sec. 2.6.1, Appendix A): on the virtually
-    extended fields its Green operator inverts div_d(C0 : grad^s_d u), the
+    extended fields its Green operator inverts div_d(C0 : grad^s_d u) (small
+    strain; div_d(C0 : grad_d u) for finite strain), the
     real-space operator with the mirror rules, off the null modes, for every
     normal-mixed condition pattern (5 pairs per axis for the normal component,
     the opposite pair for the tangential ones: the 125 cases of Eq. SGO_BCs)."""
@@ -361,6 +363,7 @@ def test_c0_green_inverts_L0(scheme):
     for choice in itertools.product(range(5), repeat=3):
         prob = W.random_small_problem(rng, n=n, scheme=scheme, bc=W.normal_mixed_bc(choice))
         prob.green = W.GREEN_C0
+        prob.finite_strain = int(finite)
         prob.lambda0, prob.mu0 = rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0)
         pl = Plan(prob)
         x = rng.standard_normal((3,) + tuple(v + 1 for v in n))
