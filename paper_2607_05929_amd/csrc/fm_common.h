@@ -31,6 +31,7 @@ __device__ __forceinline__ FM_GLOBAL T* gmut(T* p) { return (FM_GLOBAL T*)p; }
 constexpr int MAX_DEPTH = 4;
 constexpr int MAX_RADICES = 12;
 constexpr int MT_STRIDE = 160;      // reals per material table entry
+constexpr int MT_VOIGT = 32;        // offset of the Voigt (engineering-shear) stiffness of an anisotropic entry
 constexpr int NPART_S = 8;          // reals per stress partial: sum w|s|^2, sum s_c (6), pad
 constexpr int NGRAM = 10;           // upper triangle of a 4x4 Gram matrix
 

@@ -219,13 +219,17 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   }
   g.sd_nt[0] = (int)cdiv(g.N[0], SD_TX);
   g.sd_nt[1] = (int)cdiv(g.N[1], SD_TY);
-  // Layers per tile: SD_ZC, halved while the grid gives fewer than 8 blocks
-  // per compute unit: each tile recomputes one voxel layer below it, so fewer
-  // layers cost more law evaluations (elastic ones: plastic solves read
-  // their stresses from the stress pass) but fill the GPU on small grids.
+  // Layers per tile: at most SD_ZC, the node layers split evenly over the
+  // z tiles; the number of z tiles doubles while the grid gives fewer than
+  // 8 blocks per compute unit.  Each tile recomputes one voxel layer below
+  // it, so fewer layers cost more law evaluations (elastic ones: plastic
+  // solves read their stresses from the stress pass) but fill the GPU on
+  // small grids; even tiles keep the last one from being a near-empty
+  // block that still pays for its halo layer.
   const int64_t want = 8 * 256;
-  g.sd_zc = SD_ZC;
-  while (g.sd_zc > 1 && (int64_t)g.sd_nt[0] * g.sd_nt[1] * cdiv(g.N[2], g.sd_zc) < want) g.sd_zc /= 2;
+  int64_t nzt = cdiv(g.N[2], SD_ZC);
+  while (nzt < g.N[2] && (int64_t)g.sd_nt[0] * g.sd_nt[1] * nzt < want) nzt = std::min<int64_t>(2 * nzt, g.N[2]);
+  g.sd_zc = (int)cdiv(g.N[2], nzt);
   g.sd_nt[2] = (int)cdiv(g.N[2], g.sd_zc);
   g.ntile_s = g.sd_nt[0] * g.sd_nt[1] * g.sd_nt[2];
   g.ntile_v = (int)cdiv(g.Nv, SPACE_TILE);
@@ -376,21 +380,37 @@ void cubic_mandel(double C11, double C12, double C44, const double R[3][3], doub
     for (int b = 0; b < 6; ++b) out[a * 6 + b] = w[a] * w[b] * Cr[MI[a]][MJ[a]][MI[b]][MJ[b]];
 }
 
+// Packed upper triangle of the isotropic Voigt stiffness (lambda, mu).
+void voigt_iso(double lam, double mu, double* c /* 21 */) {
+  int k = 0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j, ++k)
+      c[k] = (i < 3 && j < 3) ? (i == j ? lam + 2 * mu : lam) : (i == j ? mu : 0.0);
+}
+
 int material_entry(const fm_material& mt, double* e /* MT_STRIDE */) {
   std::fill(e, e + MT_STRIDE, 0.0);
   switch (mt.law) {
     case FM_LAW_ISO:
       if (mt.p[0] < 0 || mt.p[1] < 0) return fail(FM_E_INVALID_ARG, "isotropic moduli must be >= 0");
       e[0] = mt.p[0]; e[1] = mt.p[1];
+      voigt_iso(mt.p[0], mt.p[1], e + MT_VOIGT);
       return LAW_ISO;
     case FM_LAW_CUBIC: {
       // packed upper triangle of the (symmetric) rotated Mandel stiffness
       double R[3][3], full[36];
       quat_rot(mt.quat, R);
       cubic_mandel(mt.p[0], mt.p[1], mt.p[2], R, full);
+      // and the same stiffness acting on engineering shear strains (Voigt:
+      // the Mandel entries divided by sqrt(2) per shear index)
       int k = 0;
       for (int i = 0; i < 6; ++i)
-        for (int j = i; j < 6; ++j) e[k++] = 0.5 * (full[i * 6 + j] + full[j * 6 + i]);
+        for (int j = i; j < 6; ++j) {
+          const double m = 0.5 * (full[i * 6 + j] + full[j * 6 + i]);
+          e[k] = m;
+          e[MT_VOIGT + k] = m / ((i < 3 ? 1.0 : std::sqrt(2.0)) * (j < 3 ? 1.0 : std::sqrt(2.0)));
+          ++k;
+        }
       return LAW_ANISO;
     }
     case FM_LAW_J2:

@@ -357,6 +357,37 @@ __device__ __forceinline__ void law_elastic_pts(int law, PT P, const R (&eps)[2]
   }
 }
 
+// Elastic laws with engineering shear strains (eps[3..5] twice the tensor
+// components), as the fused real-space kernel forms them, from the entry's
+// Voigt stiffness c (packed upper triangle, stored at MT_VOIGT; no Mandel
+// factors on either side); isotropic entries use lambda = c_12, mu = c_44.
+template <typename R, int NP>
+__device__ __forceinline__ void law_elastic_pts_eng(int law, const R (&c)[21], const R (&eps)[2][6], R (&sig)[2][6]) {
+  if (law == LAW_ISO) {
+    const R lam = c[1], mu = c[15], mu2 = mu + mu;
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+      const R tr = eps[r][0] + eps[r][1] + eps[r][2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) sig[r][i] = mu2 * eps[r][i] + lam * tr;
+#pragma unroll
+      for (int i = 3; i < 6; ++i) sig[r][i] = mu * eps[r][i];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < NP; ++r) mat6sym<R>(c, eps[r], sig[r]);
+  }
+}
+
+// All-zero material entry (the elastic laws give zero stress on it).
+__device__ const float k_zero_material32[MT_VOIGT + 21] = {};
+__device__ const double k_zero_material64[MT_VOIGT + 21] = {};
+template <typename R>
+__device__ __forceinline__ const FM_GLOBAL R* zero_material() {
+  if constexpr (sizeof(R) == 4) return (const FM_GLOBAL R*)k_zero_material32;
+  else return (const FM_GLOBAL R*)k_zero_material64;
+}
+
 template <typename R, typename PT>
 __device__ __forceinline__ void law_eval(int law, PT P, const R eps[6], R sig[6], const R st[7],
                                          R stn[7], R dt) {

@@ -151,7 +151,7 @@ __device__ __forceinline__ void voxel_corners(const SolveDev& s, int x, int y, i
 // corners) from the corner values, the u* gradient at the voxel centre and
 // the tetrahedron cross-term correction.  FP32 corner values are differences
 // to corner 0, which is exactly 0 and left out of the sums.
-template <typename R, int SCH>
+template <typename R, int SCH, bool ENG = false>
 __device__ __forceinline__ void strain_points(const R (&u)[3][8], const R (&gs)[3][3], const R (&hc)[3][3], R f,
                                               R eps[2][6]) {
 #pragma unroll
@@ -176,23 +176,25 @@ __device__ __forceinline__ void strain_points(const R (&u)[3][8], const R (&gs)[
         g[l][q] = a * f + gs[l][q];
         if (SCH == 1) g[l][q] += r == 0 ? -hc[l][q] : hc[l][q];
       }
+    // ENG: engineering shear strains (twice the tensor components)
+    const R hs = ENG ? (R)1 : (R)0.5;
     eps[r][0] = g[0][0]; eps[r][1] = g[1][1]; eps[r][2] = g[2][2];
-    eps[r][3] = (R)0.5 * (g[1][2] + g[2][1]);
-    eps[r][4] = (R)0.5 * (g[0][2] + g[2][0]);
-    eps[r][5] = (R)0.5 * (g[0][1] + g[1][0]);
+    eps[r][3] = ENG ? g[1][2] + g[2][1] : hs * (g[1][2] + g[2][1]);
+    eps[r][4] = ENG ? g[0][2] + g[2][0] : hs * (g[0][2] + g[2][0]);
+    eps[r][5] = ENG ? g[0][1] + g[1][0] : hs * (g[0][1] + g[1][0]);
   }
 }
 
 // Strain at the integration points (HEX1: weight (2a_l - 1)/(4h); TETRA2:
 // weight (2a_l - 1)/(2h)); the scheme is uniform over a solve, so the branch
 // is too.
-template <typename R>
+template <typename R, bool ENG = false>
 __device__ __forceinline__ void strain_from_corners(const SolveDev& s, const R (&u)[3][8], const R (&gs)[3][3],
                                                     const R (&hc)[3][3], R eps[2][6]) {
   if (s.scheme == 1)
-    strain_points<R, 1>(u, gs, hc, (R)(0.5 / s.h), eps);
+    strain_points<R, 1, ENG>(u, gs, hc, (R)(0.5 / s.h), eps);
   else
-    strain_points<R, 0>(u, gs, hc, (R)(0.25 / s.h), eps);
+    strain_points<R, 0, ENG>(u, gs, hc, (R)(0.25 / s.h), eps);
 }
 
 // Strain at the integration points of voxel (x, y, z).
@@ -291,7 +293,7 @@ __global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* _
 // owns node (x, y, z) of its lower corner; the partials also carry
 // sum |D|^2.
 // ---------------------------------------------------------------------------
-constexpr int SD_TX = 31, SD_TY = 7, SD_ZC = 16;   // node tile; voxel tile 32 x 8
+constexpr int SD_TX = 31, SD_TY = 7, SD_ZC = 32;   // node tile (at most SD_ZC layers); voxel tile 32 x 8
 constexpr int SD_VT = 256;                          // voxels per layer tile
 
 __device__ __forceinline__ int map_vox(int g, int n, int wrap) {
@@ -322,26 +324,38 @@ __device__ __forceinline__ int map_vox(int g, int n, int wrap) {
 // node then adds the partials of its four columns, dropping those of mirror
 // corners on the x and y faces.  sp / sc: stresses of the column's voxel in
 // layers J2 - 1 and J2, [point][Voigt] (HEX1: the point in both slots).
-template <typename R>
+template <typename R, bool FACE>
 __device__ __forceinline__ void column_partials(const SolveDev& s, const R (&sp)[2][6], const R (&sc)[2][6], int J2,
                                                 R* __restrict__ P) {
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    // mirror corners below / above a z face where u_q is not periodic along z
-    const bool zf = s.wrap[2] && s.kinds[q][2] != K_DFT;
-    const bool drop0 = zf && J2 == 0, drop1 = zf && J2 == s.n[2];
+    // a / b: S_lq of the points (index r) of the voxel below (b2 = 0) and
+    // above (b2 = 1) the node layer; on a z face, the mirror corners of a
+    // component not periodic along z are dropped
+    bool drop0 = false, drop1 = false;
+    if constexpr (FACE) {
+      const bool zf = s.wrap[2] && s.kinds[q][2] != K_DFT;
+      drop0 = zf && J2 == 0;
+      drop1 = zf && J2 == s.n[2];
+    }
+    R a[2][3], b[2][3];
 #pragma unroll
-    for (int b1 = 0; b1 < 2; ++b1)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int b0 = 0; b0 < 2; ++b0) {
-        const int r0 = ((b0 + b1) & 1) ? 0 : 1;      // point of the b2 = 0 corner
-        const int r1 = r0 ^ 1;                       // and of the b2 = 1 corner
-        const R x0 = sp[r0][vidx(0, q)], y0 = sp[r0][vidx(1, q)], z0 = sp[r0][vidx(2, q)];
-        const R x1 = sc[r1][vidx(0, q)], y1 = sc[r1][vidx(1, q)], z1 = sc[r1][vidx(2, q)];
-        const R t0 = (b0 ? x0 : -x0) + (b1 ? y0 : -y0) - z0;
-        const R t1 = (b0 ? x1 : -x1) + (b1 ? y1 : -y1) + z1;
-        P[(q * 4 + b1 * 2 + b0) * SD_VT] = (drop0 ? (R)0 : t0) + (drop1 ? (R)0 : t1);
+      for (int l = 0; l < 3; ++l) {
+        a[r][l] = drop0 ? (R)0 : sp[r][vidx(l, q)];
+        b[r][l] = drop1 ? (R)0 : sc[r][vidx(l, q)];
       }
+    // offsets (b0, b1) with b0 + b1 even take point 1 below and point 0
+    // above, odd ones point 0 below and point 1 above (HEX1: one point);
+    // the partial is sum_l (2 b_l - 1) S_lq over the two voxels
+    const R Xe = a[1][0] + b[0][0], Ye = a[1][1] + b[0][1], Ze = b[0][2] - a[1][2];
+    const R Xo = a[0][0] + b[1][0], Yo = a[0][1] + b[1][1], Zo = b[1][2] - a[0][2];
+    const R Se = Xe + Ye, To = Xo - Yo;
+    P[(q * 4 + 0) * SD_VT] = Ze - Se;     // (b0, b1) = (0, 0)
+    P[(q * 4 + 3) * SD_VT] = Ze + Se;     // (1, 1)
+    P[(q * 4 + 1) * SD_VT] = Zo + To;     // (1, 0)
+    P[(q * 4 + 2) * SD_VT] = Zo - To;     // (0, 1)
   }
 }
 
@@ -412,7 +426,7 @@ __device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, int J0, int J1) 
 // Divergence at the node of layer J2 (z factor fz per component: doubling on
 // a reflecting z face, 0 where not kept along z) from the column partials of
 // its four voxel columns; D written through Dn (this node in component 0).
-template <typename CT, typename R, int TR>
+template <typename CT, typename R, int TR, bool DROP>
 __device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int ly, const NodeXY<CT>& nxy,
                                          const CT (&fz)[3], FM_GLOBAL R* Dn, int64_t Nn, CT& accD,
                                          const SolveDev& s, const FM_GLOBAL Ctrl* C, int J0, int J1, int J2) {
@@ -424,7 +438,8 @@ __device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int l
 #pragma unroll
       for (int b0 = 0; b0 < 2; ++b0) {
         const CT t = P[(q * 4 + b1 * 2 + b0) * SD_VT + (ly + b1) * 32 + (lx + b0)];
-        D += ((nxy.drop >> (q * 4 + b1 * 2 + b0)) & 1) ? (CT)0 : t;
+        if constexpr (DROP) D += ((nxy.drop >> (q * 4 + b1 * 2 + b0)) & 1) ? (CT)0 : t;
+        else D += t;
       }
     const CT f = nxy.fq[q] * fz[q];
     CT Dq = D * f;
@@ -435,7 +450,7 @@ __device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int l
 }
 
 // Bytes of dynamic LDS of k_sdiv.
-__host__ __device__ inline size_t sdiv_lds_bytes(int rbytes) { return (size_t)12 * SD_VT * rbytes; }
+__host__ __device__ inline size_t sdiv_lds_bytes(int rbytes) { return (size_t)2 * 12 * SD_VT * rbytes; }
 
 // PL = 1: the group holds solves with internal variables, whose stresses
 // come from the stress pass (k_commit with SIGMA = 1); the law evaluated here
@@ -451,7 +466,7 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
   if (C->status != ST_RUNNING) return;
   if (sizeof(R) == 4 && (C->rs64 != 0) != (sizeof(CT) == 8)) return;
   extern __shared__ __align__(16) char smem[];
-  CT* sl = (CT*)smem;                                  // column partials [12][SD_VT]
+  CT* sl = (CT*)smem;                                  // column partials [2][12][SD_VT]
   const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
   const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * s.sd_zc;
   const int Z1 = min(Z0 + s.sd_zc, s.N[2]);
@@ -494,6 +509,9 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
 #pragma unroll
     for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k] = 0;
   const NodeXY<CT> nxy = node_xy<CT>(s, J0, J1);
+  // x-y mirror drops occur only on the faces of axes periodic for another
+  // component: waves without any take the plain four-column sums
+  const bool wave_drop = __any(nxy.drop != 0);
   // plastic solves read the stresses of the per-voxel stress pass
   const bool from_buf = PL && s.sig != nullptr;
   // FP32 corner carry: top corner 4 (FP64) and corners 5-7 minus it, per component
@@ -511,14 +529,19 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
     {
       const int vz = map_vox(zl, n2, s.wrap[2]);
       const int law = gconst(s.mlaw)[mt_cur];
-      const FM_GLOBAL R* P = gconst((const R*)s.mtab) + (int64_t)mt_cur * MT_STRIDE;
+      // halo voxels across faces of axes periodic for no component hold zero
+      // stress: their elastic law reads the all-zero entry
+      const bool zero_halo = zero_xy || (!s.wrap[2] && (zl < 0 || zl >= n2));
+      const FM_GLOBAL R* P = (!from_buf && zero_halo) ? zero_material<R>()
+                                                      : gconst((const R*)s.mtab) + (int64_t)mt_cur * MT_STRIDE;
       CT eps[2][6];
       if (!from_buf) {
         CT u[3][8], gs[3][3];
         if constexpr (sizeof(CT) == 4) {
           // FP32: FP64 differences to corner 0, with the bottom face taken
           // from the previous layer's top face when the layers are adjacent
-          // (same nodes, same differences: bitwise the full computation)
+          // (its differences to its own corner 0 formed from the rounded
+          // top-face differences)
           const bool carry = zl >= Z0 && vz == vz_prev + 1;
           const int64_t base = (int64_t)vz * N01 + (int64_t)vy * s.N[0] + vx;
 #pragma unroll
@@ -542,7 +565,7 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
             for (int c = 0; c < 4; ++c) u[q][4 + c] = (CT)(top[c] - u0);
             cu4[q] = top[0];
 #pragma unroll
-            for (int c = 1; c < 4; ++c) cdt[q][c - 1] = (CT)(top[c] - top[0]);
+            for (int c = 1; c < 4; ++c) cdt[q][c - 1] = u[q][4 + c] - u[q][4];
           }
           vz_prev = vz;
         } else {
@@ -553,11 +576,17 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
         for (int l = 0; l < 3; ++l)
 #pragma unroll
           for (int q = 0; q < 3; ++q) gs[l][q] = gA[l][q] + gB[l][q] * zc;
-        strain_from_corners<CT>(s, u, gs, hc, eps);
+        strain_from_corners<CT, true>(s, u, gs, hc, eps);
+      }
+      // the Voigt stiffness of the voxel (read for every law, outside the
+      // law's branch, so that the loads issue together)
+      CT cv[21];
+      if (!from_buf) {
+#pragma unroll
+        for (int k = 0; k < 21; ++k) cv[k] = (CT)P[MT_VOIGT + k];
       }
       const int64_t v = ((int64_t)vz * n1 + vy) * n0 + vx;
       const bool own = own_xy && zl >= Z0 && zl < n2;
-      const bool zero_halo = zero_xy || (!s.wrap[2] && (zl < 0 || zl >= n2));
       // the stresses of the voxel's points (one law branch per voxel, so the
       // material entry is read once for both points)
       CT sig2[2][6];
@@ -569,18 +598,18 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
             for (int k = 0; k < 6; ++k) sig2[r][k] = gconst((const R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v];
       } else if (s.nppv == 2) {
         // solves without internal variables: elastic laws only
-        law_elastic_pts<CT, 2>(law, P, eps, sig2);
+        law_elastic_pts_eng<CT, 2>(law, cv, eps, sig2);
       } else {
-        law_elastic_pts<CT, 1>(law, P, eps, sig2);
+        law_elastic_pts_eng<CT, 1>(law, cv, eps, sig2);
       }
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         if (r >= s.nppv) break;
         const CT (&sig)[6] = sig2[r];
-        // halo voxels across faces of axes periodic for no component hold zero
+        // (stresses read from the stress buffer are zeroed here)
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          const CT val = zero_halo ? (CT)0 : sig[k];
+          const CT val = (from_buf && zero_halo) ? (CT)0 : sig[k];
           scur[0][k] = r == 0 ? val : scur[0][k];
           scur[1][k] = r == 0 ? val : (r == 1 ? val : scur[1][k]);
         }
@@ -596,7 +625,12 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
       }
     }
     if (zl >= Z0) {
-      column_partials<CT>(s, sprev, scur, zl, sl + threadIdx.x);
+      // the partials of consecutive layers alternate between two buffers: a
+      // layer's writes come after the barrier of the layer before, which
+      // every thread passes only once it has read the buffer two layers back
+      CT* slb = sl + (zl & 1) * 12 * SD_VT;
+      if (zl == 0 || zl == n2) column_partials<CT, true>(s, sprev, scur, zl, slb + threadIdx.x);
+      else column_partials<CT, false>(s, sprev, scur, zl, slb + threadIdx.x);
       CT fz[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -604,15 +638,212 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
         fz[q] = node_kept(s.kinds[q][2], n2, zl) ? (face ? (CT)2 : (CT)1) : (CT)0;
       }
       __syncthreads();
-      if (has_node)
-        node_div<CT, R, TR>(sl, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx, Y0 + ly, zl);
-      __syncthreads();
+      if (has_node) {
+        if (wave_drop)
+          node_div<CT, R, TR, true>(slb, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
+                                    Y0 + ly, zl);
+        else
+          node_div<CT, R, TR, false>(slb, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
+                                     Y0 + ly, zl);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k];
     mt_cur = mt_next;
+  }
+  __shared__ double outp[8];
+  double accd[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) accd[i] = (double)acc[i];
+  block_sum<8>(accd, outp);
+  __syncthreads();
+  if (threadIdx.x < 8) gmut(s.part_s)[(int64_t)w.y * NPART_S + threadIdx.x] = outp[threadIdx.x];
+}
+
+// FP32 elastic groups: the same tile as sdiv_tile, software-pipelined over
+// the voxel layers.  The FP64 top face of layer z + 1's voxel is loaded as
+// soon as layer z's corner differences are formed, its Voigt stiffness and
+// law (and the material id of layer z + 2) as soon as layer z's law has
+// been evaluated, so that their latency overlaps the rest of the layer
+// (vector-memory loads complete in order, and a wait for an earlier load
+// leaves the later ones in flight).  The bottom face of a
+// voxel comes from the previous layer's top face (carry) or, on the first
+// layer of the tile and across a periodic wrap, from a load of its own.
+template <typename R, int TR>
+__device__ __forceinline__ void sdiv_tile_f32(const SolveDev* __restrict__ S, const int2 w) {
+  typedef float CT;
+  const SolveDev& s = S[w.x];
+  const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
+  if (C->status != ST_RUNNING) return;
+  if (C->rs64 != 0) return;
+  extern __shared__ __align__(16) char smem[];
+  CT* sl = (CT*)smem;                                  // column partials [2][12][SD_VT]
+  const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
+  const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * s.sd_zc;
+  const int Z1 = min(Z0 + s.sd_zc, s.N[2]);
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  const int n0 = s.n[0], n1 = s.n[1], n2 = s.n[2];
+  const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
+  const int vx = map_vox(gx, n0, s.wrap[0]), vy = map_vox(gy, n1, s.wrap[1]);
+  const bool own_xy = lx >= 1 && ly >= 1 && gx < n0 && gy < n1;
+  const bool zero_xy = (!s.wrap[0] && (gx < 0 || gx >= n0)) || (!s.wrap[1] && (gy < 0 || gy >= n1));
+  const int J0 = X0 + lx, J1 = Y0 + ly;
+  const bool has_node = lx < SD_TX && ly < SD_TY && J0 < s.N[0] && J1 < s.N[1];
+  const FM_GLOBAL uint16_t* mat = gconst(s.mat);
+  const FM_GLOBAL int* mlaw = gconst(s.mlaw);
+  const FM_GLOBAL R* mtab = gconst((const R*)s.mtab);
+  const CT wip = (CT)1 / (CT)s.nppv;
+  CT acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  CT gA[3][3], gB[3][3], hc[3][3];
+  {
+    const float xc = (float)((vx + 0.5) * s.h), yc = (float)((vy + 0.5) * s.h);
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        gA[l][q] = C->g32[q * 3 + l] + C->h32[(q * 3 + l) * 3] * xc + C->h32[(q * 3 + l) * 3 + 1] * yc;
+        gB[l][q] = C->h32[(q * 3 + l) * 3 + 2];
+        hc[l][q] = C->hc32[l * 3 + q];
+      }
+  }
+  CT sprev[2][6], scur[2][6];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k] = 0;
+  const NodeXY<CT> nxy = node_xy<CT>(s, J0, J1);
+  const bool wave_drop = __any(nxy.drop != 0);
+  const int64_t N0 = s.N[0], N01 = (int64_t)s.N[0] * s.N[1], Nn = s.Nn;
+  const FM_GLOBAL double* uf = gconst(s.uf);
+  FM_GLOBAL R* Dcol = gmut((R*)s.Dring) + (int64_t)(C->m % s.depth) * 3 * s.Nn + (int64_t)J1 * s.N[0] + J0;
+  const int64_t col = (int64_t)vy * n0 + vx;            // voxel column
+  const int64_t ncol = (int64_t)vy * N0 + vx;           // its corner-0 node column
+  auto vz_of = [&](int z) { return map_vox(z, n2, s.wrap[2]); };
+  auto halo_z = [&](int z) { return !s.wrap[2] && (z < 0 || z >= n2); };
+  // stage of the layer being computed: raw top face, stiffness, law
+  double top[3][4];
+  CT cv[21];
+  int law;
+  auto load_top = [&](int vz, double (&t)[3][4]) {
+    const FM_GLOBAL double* b = uf + (int64_t)(vz + 1) * N01 + ncol;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[q][c] = b[q * Nn + (c & 1) + (c >> 1) * N0];
+  };
+  auto load_law = [&](int z, int mt, CT (&c)[21], int& lw) {
+    const FM_GLOBAL R* P = (zero_xy || halo_z(z)) ? zero_material<R>() : mtab + (int64_t)mt * MT_STRIDE;
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c[k] = (CT)P[MT_VOIGT + k];
+    lw = mlaw[mt];
+  };
+  // prologue: the first layer's stage, the next layer's material
+  int vz = vz_of(Z0 - 1);
+  {
+    const int mt0 = mat[(int64_t)vz * n1 * n0 + col];
+    load_top(vz, top);
+    load_law(Z0 - 1, mt0, cv, law);
+  }
+  int mt1 = mat[(int64_t)vz_of(Z0) * n1 * n0 + col];
+  double cu4[3] = {0, 0, 0};
+  CT cdt[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  int vz_prev = -2;
+  for (int zl = Z0 - 1; zl < Z1; ++zl) {
+    // corner differences of this layer's voxel (FP64, rounded once)
+    CT u[3][8];
+    const bool carry = vz == vz_prev + 1;
+    if (!carry) {
+      const FM_GLOBAL double* b = uf + (int64_t)vz * N01 + ncol;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        double bt[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bt[c] = b[q * Nn + (c & 1) + (c >> 1) * N0];
+        cu4[q] = bt[0];
+#pragma unroll
+        for (int c = 1; c < 4; ++c) cdt[q][c - 1] = (CT)(bt[c] - bt[0]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double u0 = cu4[q];
+      u[q][0] = 0;
+#pragma unroll
+      for (int c = 1; c < 4; ++c) u[q][c] = cdt[q][c - 1];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) u[q][4 + c] = (CT)(top[q][c] - u0);
+      cu4[q] = top[q][0];
+#pragma unroll
+      for (int c = 1; c < 4; ++c) cdt[q][c - 1] = u[q][4 + c] - u[q][4];
+    }
+    vz_prev = vz;
+    // issue the next layer's top face (the last layer reads valid data it
+    // does not use)
+    const int vzn = vz_of(zl + 1);
+    load_top(vzn, top);
+    {
+      CT eps[2][6], gs[3][3];
+      const CT zc = (CT)((vz + 0.5) * s.h);
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gs[l][q] = gA[l][q] + gB[l][q] * zc;
+      strain_from_corners<CT, true>(s, u, gs, hc, eps);
+      const bool own = own_xy && zl >= Z0 && zl < n2;
+      CT sig2[2][6];
+      if (s.nppv == 2) law_elastic_pts_eng<CT, 2>(law, cv, eps, sig2);
+      else law_elastic_pts_eng<CT, 1>(law, cv, eps, sig2);
+      // and, the stiffness consumed, the next layer's stiffness and law and
+      // the material of the layer after it
+      load_law(zl + 1, mt1, cv, law);
+      mt1 = mat[(int64_t)vz_of(zl + 2) * n1 * n0 + col];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if (r >= s.nppv) break;
+        const CT (&sig)[6] = sig2[r];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          scur[0][k] = r == 0 ? sig[k] : scur[0][k];
+          scur[1][k] = sig[k];
+        }
+        if (own) {
+          CT n2s = 0;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            n2s += (k < 3 ? (CT)1 : (CT)2) * sig[k] * sig[k];
+            acc[1 + k] += wip * sig[k];
+          }
+          acc[0] += wip * n2s;
+        }
+      }
+    }
+    if (zl >= Z0) {
+      CT* slb = sl + (zl & 1) * 12 * SD_VT;
+      if (zl == 0 || zl == n2) column_partials<CT, true>(s, sprev, scur, zl, slb + threadIdx.x);
+      else column_partials<CT, false>(s, sprev, scur, zl, slb + threadIdx.x);
+      CT fz[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const bool face = s.kinds[q][2] != K_DFT && (zl == 0 || zl == n2);
+        fz[q] = node_kept(s.kinds[q][2], n2, zl) ? (face ? (CT)2 : (CT)1) : (CT)0;
+      }
+      __syncthreads();
+      if (has_node) {
+        if (wave_drop)
+          node_div<CT, R, TR, true>(slb, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
+                                    Y0 + ly, zl);
+        else
+          node_div<CT, R, TR, false>(slb, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
+                                     Y0 + ly, zl);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sprev[r][k] = scur[r][k];
+    vz = vzn;
   }
   __shared__ double outp[8];
   double accd[8];
@@ -630,9 +861,11 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
 // TR = 1 adds the applied-traction term D* at the loaded faces (groups whose
 // load paths carry tractions; the common kernel carries no traction code).
 template <typename R, int PL, typename CT = R, int TR = 0>
-__global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : 4)
+__global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : (sizeof(R) == 4 && PL == 0 ? 3 : 4))
     k_sdiv(const SolveDev* __restrict__ S, const int2* __restrict__ work, int nwork) {
-  if constexpr (sizeof(R) == 4 && sizeof(CT) == 8) {
+  if constexpr (sizeof(R) == 4 && sizeof(CT) == 4 && PL == 0) {
+    sdiv_tile_f32<R, TR>(S, work[blockIdx.x]);
+  } else if constexpr (sizeof(R) == 4 && sizeof(CT) == 8) {
     for (int i = blockIdx.x; i < nwork; i += gridDim.x) {
       sdiv_tile<R, PL, CT, TR>(S, work[i]);
       __syncthreads();
