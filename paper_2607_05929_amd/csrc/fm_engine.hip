@@ -226,7 +226,7 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   // solves read their stresses from the stress pass) but fill the GPU on
   // small grids; even tiles keep the last one from being a near-empty
   // block that still pays for its halo layer.
-  const int64_t want = 8 * 256;
+  const int64_t want = SD_WANT_BLOCKS;
   int64_t nzt = cdiv(g.N[2], SD_ZC);
   while (nzt < g.N[2] && (int64_t)g.sd_nt[0] * g.sd_nt[1] * nzt < want) nzt = std::min<int64_t>(2 * nzt, g.N[2]);
   g.sd_zc = (int)cdiv(g.N[2], nzt);
@@ -273,6 +273,24 @@ inline bool slot_used(const Geometry& g, int pass) {
 inline int slot_axis(int pass) { return pass == 0 || pass == 4 ? 0 : (pass == 1 || pass == 3 ? 1 : 2); }
 
 size_t group_bytes_for(int nsolves, int64_t tiles_total[NWL]);
+
+// Stress-divergence tiling of a group member.  A lone solve keeps the
+// tiling of its geometry, which shortens the tiles until the grid fills the
+// GPU; in a group whose members together give enough tiles, every member
+// takes tiles of up to SD_ZC layers, since each tile recomputes one voxel
+// layer below it (a one-layer tile evaluates the law twice per voxel).
+// The deep tiling never has more tiles than the geometry's, for which the
+// partial buffers and work lists are sized.
+struct SdivTiling {
+  int zc, nz, ntile;
+};
+inline SdivTiling sdiv_tiling(const Geometry& g, bool deep) {
+  if (!deep) return {g.sd_zc, g.sd_nt[2], g.ntile_s};
+  const int64_t nzt = cdiv(g.N[2], SD_ZC);
+  const int zc = std::max(g.sd_zc, (int)cdiv(g.N[2], nzt));
+  const int nz = (int)cdiv(g.N[2], zc);
+  return {zc, nz, g.sd_nt[0] * g.sd_nt[1] * nz};
+}
 
 void tiles_of(const Geometry& g, int64_t t[NWL]) {
   for (int k = 0; k < NWL; ++k) t[k] = 0;
@@ -807,13 +825,20 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
   std::vector<int> ids(ns);
   for (int k = 0; k < NPASS; ++k)
     for (int b = 0; b < NBUCKET; ++b) G.blds[k][b] = 0;
+  int64_t deep_tiles = 0;
+  for (int i = 0; i < ns; ++i) deep_tiles += sdiv_tiling(plans[i]->g, true).ntile;
+  const bool deep = ns > 1 && deep_tiles >= SD_WANT_BLOCKS;
   for (int i = 0; i < ns; ++i) {
     fm_plan* p = plans[i];
     S[i] = p->sd;
+    const SdivTiling st = sdiv_tiling(p->g, deep);
+    S[i].sd_zc = st.zc;
+    S[i].sd_nt[2] = st.nz;
+    S[i].ntile_s = st.ntile;
     ids[i] = i;
     for (int ty = 0; ty < p->g.ntile_v; ++ty) wl[0].push_back(make_int2(i, ty));
     for (int ty = 0; ty < p->g.ntile_d; ++ty) wl[1].push_back(make_int2(i, ty));
-    for (int ty = 0; ty < p->g.ntile_s; ++ty) wl[2].push_back(make_int2(i, ty));
+    for (int ty = 0; ty < st.ntile; ++ty) wl[2].push_back(make_int2(i, ty));
     for (int ty = 0; ty < p->g.ntile_c0; ++ty) wl[3].push_back(make_int2(i, ty));
     for (int q = 0; q < 3; ++q)
       for (int pass = 0; pass < NPASS; ++pass) {

@@ -295,6 +295,7 @@ __global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* _
 // ---------------------------------------------------------------------------
 constexpr int SD_TX = 31, SD_TY = 7, SD_ZC = 32;   // node tile (at most SD_ZC layers); voxel tile 32 x 8
 constexpr int SD_VT = 256;                          // voxels per layer tile
+constexpr int SD_WANT_BLOCKS = 8 * 256;             // stress-divergence tiles that fill the GPU
 
 __device__ __forceinline__ int map_vox(int g, int n, int wrap) {
   if (g < 0) return wrap ? n - 1 : 0;
