@@ -214,14 +214,18 @@ def serving_sample(B, W, prec, count=16, rate=200.0, sizes=(32, 64, 96), n_steps
     reqs = W.serving_stream(count=count, rate=rate, sizes=sizes, n_steps=n_steps, prec=prec)
     srv = B.Server(arena_bytes=arena_gib << 30, max_active=64)
     t0 = time.time()
-    tickets, k = [], 0
+    tickets, k, n_done = [], 0, 0
     while True:
         now = time.time() - t0
         while k < len(reqs) and reqs[k].arrival_s <= now:
             tickets.append(srv.submit(reqs[k].problem, arrival_s=reqs[k].arrival_s, now_s=now, prec=prec))
             k += 1
         srv.step(4, time.time() - t0)
-        if k == len(reqs) and all(srv.poll(t)[0] == 2 for t in tickets):
+        done = sum(1 for t in tickets if srv.poll(t)[0] == 2)
+        if log and done > n_done:
+            log(f"serving: {done}/{len(reqs)} requests done after {time.time() - t0:.1f} s")
+        n_done = done
+        if k == len(reqs) and done == len(reqs):
             break
     wall = time.time() - t0
     st = srv.stats()
@@ -239,7 +243,7 @@ def serving_sweep(B, W, rates=(2.0, 4.0, 8.0, 16.0, 32.0), count=40, sizes=(32,)
     which p99 latency stays within twice the p50 of the lowest rate."""
     out = []
     for r in rates:
-        s = serving_sample(B, W, W.FP32_MIXED, count=count, rate=r, sizes=sizes, n_steps=10, arena_gib=16)
+        s = serving_sample(B, W, W.FP32_MIXED, count=count, rate=r, sizes=sizes, n_steps=10, arena_gib=16, log=log)
         out.append(s)
         if log:
             log(f"sweep rate {r}: p50 {s['p50_latency_s']:.3f} s p99 {s['p99_latency_s']:.3f} s")
@@ -423,13 +427,13 @@ def main():
     if not args.no_serving:
         serving = {}
         for name, prec in (("fp32", W.FP32_MIXED), ("fp64", W.FP64)):
-            serving[name] = serving_sample(B, W, prec)
+            serving[name] = serving_sample(B, W, prec, log=log if args.serving_full else None)
             sv = serving[name]
             log(f"serving {name}: {sv['completed']} requests, p50 {sv['p50_latency_s']:.3f} s, "
                 f"p99 {sv['p99_latency_s']:.3f} s, {sv['throughput_voxel_iter_s']:.3e} voxel-iter/s")
         if args.serving_full:
             for name, prec in (("fp32_full_range", W.FP32_MIXED), ("fp64_full_range", W.FP64)):
-                serving[name] = serving_sample(B, W, prec, count=12, sizes=(32, 64, 96, 128, 160, 192))
+                serving[name] = serving_sample(B, W, prec, count=12, sizes=(32, 64, 96, 128, 160, 192), log=log)
                 sv = serving[name]
                 log(f"serving {name}: p50 {sv['p50_latency_s']:.3f} s, p99 {sv['p99_latency_s']:.3f} s, "
                     f"{sv['throughput_voxel_iter_s']:.3e} voxel-iter/s")

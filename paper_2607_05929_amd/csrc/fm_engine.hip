@@ -1666,7 +1666,11 @@ int fm_set_material(fm_plan* p, const int32_t* d_mat_id, int32_t n_mat, const fm
   if (hbad) return fail(FM_E_INVALID_ARG, "material id out of range");
   HIPCHK(hipMemsetAsync(ws + p->lay.uf, 0, 8 * 3 * (size_t)p->g.Nn, p->stream));
   HIPCHK(hipMemsetAsync(ws + p->lay.dring, 0, R * p->g.depth * 3 * (size_t)p->g.Nn, p->stream));
-  if (p->d.with_state) HIPCHK(hipMemsetAsync(ws + p->lay.state, 0, R * 7 * p->g.nppv * (size_t)p->g.Nv, p->stream));
+  if (p->d.with_state) {
+    HIPCHK(hipMemsetAsync(ws + p->lay.state, 0, R * 7 * p->g.nppv * (size_t)p->g.Nv, p->stream));
+    // the stress of the previous iterate, a start of the crystal-plasticity solve
+    HIPCHK(hipMemsetAsync(ws + p->lay.sig, 0, R * 6 * p->g.nppv * (size_t)p->g.Nv, p->stream));
+  }
   HIPCHK(hipStreamSynchronize(p->stream));
   p->material_set = true;
   p->n_mat = n_mat;

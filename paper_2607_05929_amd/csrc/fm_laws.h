@@ -133,10 +133,15 @@ __device__ __forceinline__ void mandel_rotate(const R (&Rm)[3][3], const R a[6],
 // (the equations are invariant under the rotation; there the Schmid tensors
 // are constants and the cubic compliance has three entries): Newton on
 // sigma_M, dGamma with backtracking, started from the elastic predictor
-// scaled to |tau|/tau_c <= 2; stops at the tolerance or when no backtracked
-// step lowers the residual.
+// scaled to |tau|/tau_c <= 2, or from the stress sp of the point's previous
+// evaluation (Mandel, sample frame; with the slip its rates give at the
+// increment's initial hardness) when that has the smaller residual: within
+// an increment the strain changes little between iterations, so the
+// previous stress is a few Newton steps closer to the solution.  Stops at
+// the tolerance or when no backtracked step lowers the residual.
 template <typename R, typename PT>
-__device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[6], R epm[6], R& Gout) {
+__device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[6], R epm[6], R& Gout,
+                          const R* sp = nullptr) {
   R Rm[3][3];
 #pragma unroll
   for (int i = 0; i < 9; ++i) Rm[i / 3][i % 3] = P[i];
@@ -209,6 +214,22 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
   // (the slip rates are recomputed where needed rather than kept: registers)
   R Rs[6], Rg, tc;
   R nr = resid(sig, dG, Rs, Rg, tc);
+  if (sp) {
+    R sc[6];
+    mandel_rotate<R>(Rm, sp, sc, true);
+    const R itc0 = (R)1 / (tau0 + (taus - tau0) * (1 - exp(-th0 * Gn * ihs)));
+    R d0 = 0;
+#pragma unroll
+    for (int s_ = 0; s_ < 12; ++s_) d0 += fabs(rate(tau_of(sc, s_) * itc0));
+    d0 *= dt;
+    R Rs_b[6], Rg_b, tc_b;
+    const R nr_b = resid(sc, d0, Rs_b, Rg_b, tc_b);
+    if (nr_b < nr) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) { sig[i] = sc[i]; Rs[i] = Rs_b[i]; }
+      dG = d0; Rg = Rg_b; tc = tc_b; nr = nr_b;
+    }
+  }
   for (int it = 0; it < 80 && nr >= LawTol<R>::cp; ++it) {
     R J[7][8];
     const R hG = th0 * exp(-th0 * (Gn + dG) * ihs);
@@ -388,9 +409,11 @@ __device__ __forceinline__ const FM_GLOBAL R* zero_material() {
   else return (const FM_GLOBAL R*)k_zero_material64;
 }
 
+// sp: the stress of the point's previous evaluation (Voigt), a start for
+// the crystal-plasticity Newton solve, or null.
 template <typename R, typename PT>
 __device__ __forceinline__ void law_eval(int law, PT P, const R eps[6], R sig[6], const R st[7],
-                                         R stn[7], R dt) {
+                                         R stn[7], R dt, const R* sp = nullptr) {
   if (law == LAW_ISO) {
     const R lam = P[0], mu = P[1];
     const R tr = eps[0] + eps[1] + eps[2];
@@ -437,10 +460,11 @@ __device__ __forceinline__ void law_eval(int law, PT P, const R eps[6], R sig[6]
       stn[6] = st[6] + dp;
     }
   } else {
-    R em[6], epn[6], sm[6], epm[6], G;
+    R em[6], epn[6], sm[6], epm[6], G, spm[6];
     to_mandel(eps, em);
     to_mandel(st, epn);
-    cp_update<R>(P, em, epn, st[6], dt, sm, epm, G);
+    if (sp) to_mandel(sp, spm);
+    cp_update<R>(P, em, epn, st[6], dt, sm, epm, G, sp ? spm : nullptr);
     from_mandel(sm, sig);
     from_mandel(epm, stn);
     stn[6] = G;
@@ -457,11 +481,15 @@ __device__ __forceinline__ void law_eval(int law, PT P, const R eps[6], R sig[6]
 // is a smooth function of u^f and the FP32 solve converges as the FP64 one.
 template <typename R, typename PT>
 __device__ __forceinline__ void law_eval_e64(int law, PT P, const double eps[6], R sig[6], const R st[7], R stn[7],
-                                             double dt) {
-  double s[6], a[7], b[7];
+                                             double dt, const R* sp = nullptr) {
+  double s[6], a[7], b[7], spd[6];
 #pragma unroll
   for (int i = 0; i < 7; ++i) a[i] = st[i];
-  law_eval<double>(law, P, eps, s, a, b, dt);
+  if (sp) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) spd[i] = sp[i];
+  }
+  law_eval<double>(law, P, eps, s, a, b, dt, sp ? spd : nullptr);
 #pragma unroll
   for (int i = 0; i < 6; ++i) sig[i] = (R)s[i];
 #pragma unroll

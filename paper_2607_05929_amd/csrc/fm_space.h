@@ -252,8 +252,19 @@ __global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* _
         for (int k = 0; k < 7; ++k) st[k] = 0;
       }
       R sig[6];
-      if constexpr (PL != 0) law_eval_e64<R>(law, P, eps[r], sig, st, stn, C->dt);
-      else law_elastic<R>(law, P, eps[r], sig, st, stn);
+      if constexpr (PL != 0) {
+        // crystal plasticity starts its Newton solve from the point's stress
+        // of the previous iteration when that is closer (zero before the first)
+        R sp[6];
+        const bool warm = s.sig != nullptr && law == LAW_CP;
+        if (warm) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) sp[k] = gconst((const R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v];
+        }
+        law_eval_e64<R>(law, P, eps[r], sig, st, stn, C->dt, warm ? sp : nullptr);
+      } else {
+        law_elastic<R>(law, P, eps[r], sig, st, stn);
+      }
       if (SIGMA) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) gmut((R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v] = sig[k];
