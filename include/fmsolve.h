@@ -137,7 +137,14 @@ typedef struct {
  * i (Sec. 2.2: sigma_iq (-1)^(a+1) = T*_q, i.e. the traction vector
  * sigma n); it may be non-zero only where u_q is Neumann on that face
  * (FM_E_BC otherwise).  The solver adds D* = div_d P*, the divergence of the
- * applied stress that is 2 T* on the face's mirror voxels (Fig. NeumannBC). */
+ * applied stress that is 2 T* on the face's mirror voxels (Fig. NeumannBC).
+ * ustar, optional (NULL: none), adds a nodal field to u*: device FP64, 3 x
+ * nodes in the layout of fm_outputs.u (component-major, x fastest), read
+ * during the increment's begin and the solve's end, so it must stay valid
+ * until fm_solve returns (fm_batch_solve: returns; server: the request
+ * completes).  As the paper's u* (Sec. 2.2, Algorithm 1 set-up) only its
+ * values on the Dirichlet faces of each component shape the solution; the
+ * rest is absorbed by u^f. */
 typedef struct {
   double  c[3];
   double  G[3][3];
@@ -146,6 +153,7 @@ typedef struct {
   double  mixed_target[6];
   double  dt;
   double  traction[3][2][3];
+  const double* ustar;
 } fm_load_step;
 
 /* Outputs; every pointer may be NULL.  u, eps, sig are device pointers
@@ -237,7 +245,8 @@ int fm_batch_solve(fm_plan* const* plans, int32_t n_plans,
  * writes D = div_d sigma at the nodes (Algorithm 1; 0 at dismissed nodes)
  * to d_D (device FP64, 3 x nodes) and the equilibrium error and macroscopic
  * stress to the host (err: 1 double, macro: 6 doubles, either may be NULL).
- * Overwrites the plan's displacement. */
+ * d_uf is u^f alone; a nodal u* of the step is added to it.  Overwrites the
+ * plan's displacement. */
 int fm_apply_green(fm_plan* plan, const double* d_x, double* d_w);
 int fm_residual(fm_plan* plan, const fm_load_step* step, const double* d_uf, double* d_D,
                 double* err, double* macro);

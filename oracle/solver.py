@@ -65,7 +65,9 @@ class Plan:
         self.X = np.meshgrid(j[0], j[1], j[2], indexing="ij")
 
     # -- operators -----------------------------------------------------------
-    def ustar(self, c, G, H):
+    def ustar(self, c, G, H, nodal=None):
+        """u* at the nodes (Algorithm 1 set-up): the quadratic polynomial
+        c + G x + x.H.x / 2, plus an optional nodal field (3, N1, N2, N3)."""
         X = self.X
         u = np.zeros((3,) + X[0].shape)
         for q in range(3):
@@ -74,6 +76,8 @@ class Plan:
                 u[q] += G[q, l] * X[l]
                 for m in range(3):
                     u[q] += 0.5 * H[q, l, m] * X[l] * X[m]
+        if nodal is not None:
+            u += np.asarray(nodal, dtype=np.float64)
         return u
 
     def grad(self, u):
@@ -189,7 +193,7 @@ def solve(prob, callback=None):
         converged = False
         m = 0
         while True:
-            us = pl.ustar(step.c, G, step.H)
+            us = pl.ustar(step.c, G, step.H, getattr(step, "ustar_nodal", None))
             gu = pl.grad(uf) + pl.grad(us)            # gu[..., l, q] = D_l u_q
             if fs:
                 # Lagrangian finite strain (Sec. 2.2): F[q, J] = delta + D_J u_q,
@@ -253,7 +257,7 @@ def solve(prob, callback=None):
         macro.append(mvo)
         iters.append(m)
         conv.append(converged)
-    us = pl.ustar(prob.steps[-1].c, Gs[-1], prob.steps[-1].H)
+    us = pl.ustar(prob.steps[-1].c, Gs[-1], prob.steps[-1].H, getattr(prob.steps[-1], "ustar_nodal", None))
     u = uf + us
     if fs:
         # outputs of a finite-strain solve: Green-Lagrange strain and Cauchy stress

@@ -39,7 +39,7 @@ class Material(C.Structure):
 class LoadStep(C.Structure):
     _fields_ = [("c", C.c_double * 3), ("G", C.c_double * 9), ("H", C.c_double * 27),
                 ("mixed_mask", C.c_int32 * 6), ("mixed_target", C.c_double * 6),
-                ("dt", C.c_double), ("traction", C.c_double * 18)]
+                ("dt", C.c_double), ("traction", C.c_double * 18), ("ustar", C.c_void_p)]
 
 
 class Outputs(C.Structure):
@@ -190,6 +190,7 @@ def material_table(prob):
 
 def load_steps(steps):
     arr = (LoadStep * len(steps))()
+    keep = []
     for k, s in enumerate(steps):
         e = arr[k]
         for i in range(3):
@@ -207,6 +208,16 @@ def load_steps(steps):
         T = np.asarray(getattr(s, "traction", np.zeros((3, 2, 3))), dtype=np.float64).reshape(-1)
         for i in range(18):
             e.traction[i] = T[i]
+        nod = getattr(s, "ustar_nodal", None)
+        if nod is not None:
+            # (3, N1, N2, N3) -> the library's node layout (3, N3, N2, N1), on the device;
+            # the array keeps the tensor alive as long as the steps are in use
+            torch = _torch()
+            t = torch.from_numpy(np.ascontiguousarray(np.asarray(nod, dtype=np.float64).transpose(0, 3, 2, 1)))
+            t = t.to("cuda")
+            keep.append(t)
+            e.ustar = t.data_ptr()
+    arr._keep = keep
     return arr
 
 
@@ -488,9 +499,10 @@ class Server:
         t = C.c_uint64()
         check(lib().fm_server_submit(self.handle, C.byref(req), float(now_s), C.byref(t)),
               "fm_server_submit")
-        # the library copies the request's inputs; it writes its results into
-        # these two host arrays when the solve completes
-        self.keep[t.value] = (macro, iters)
+        # the library copies the request's inputs (a nodal u* stays on the
+        # device: its tensors are kept until the result is released); it
+        # writes its results into these two host arrays when the solve completes
+        self.keep[t.value] = (macro, iters, st._keep)
         return t.value
 
     def step(self, iters, now_s):
@@ -504,7 +516,7 @@ class Server:
         return int(st.value), float(lat.value)
 
     def result(self, ticket):
-        macro, iters = self.keep[ticket]
+        macro, iters = self.keep[ticket][:2]
         return {"macro_sigma": macro, "iters": iters.tolist()}
 
     def release(self, ticket):

@@ -478,6 +478,16 @@ __global__ void k_cast_f(const double* in, float* out, int64_t n) {
   if (i < n) out[i] = (float)in[i];
 }
 
+// u^f += a v over n reals: a load step's nodal u* is folded into the
+// displacement buffer for the increment (a = 1) and taken out at its end
+// (a = -1), so that every kernel reads u^f + u*_nodal where it reads u^f.
+// The update of an iteration adds increments that vanish on the dismissed
+// nodes, so the buffer keeps the prescribed values there.
+__global__ void k_add_nodal(double* __restrict__ uf, const double* __restrict__ v, double a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) uf[i] += a * v[i];
+}
+
 __global__ void k_cast_d(const float* in, double* out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) out[i] = (double)in[i];
@@ -507,6 +517,7 @@ struct fm_plan {
   int n_mat = 0;
   int64_t total_iters = 0;
   Group* self = nullptr;   // single-plan group
+  const double* ustar_cur = nullptr;   // nodal u* folded into u^f for the current increment
   // per-solve bookkeeping used by batch / server drivers
   int cur_step = 0;
   int rc = FM_OK;
@@ -1399,6 +1410,24 @@ int begin_step(fm_plan* p, const fm_load_step& st, int t, const Ctrl* prev) {
   }
   ctrl_fp32_copies(c, p->d.scheme == FM_TETRA2 ? 0.5 * p->d.h : 0.0);
   HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, p->stream));
+  if (st.ustar) {
+    const int64_t n3 = 3 * p->g.Nn;
+    hipLaunchKernelGGL(k_add_nodal, dim3(cdiv(n3, 256)), dim3(256), 0, p->stream, (double*)(p->ws + p->lay.uf),
+                       st.ustar, 1.0, n3);
+    HIPCHK(hipGetLastError());
+  }
+  p->ustar_cur = st.ustar;
+  return 0;
+}
+
+// Takes the increment's nodal u* back out of the displacement buffer.
+int unfold_ustar(fm_plan* p) {
+  if (!p->ustar_cur) return 0;
+  const int64_t n3 = 3 * p->g.Nn;
+  hipLaunchKernelGGL(k_add_nodal, dim3(cdiv(n3, 256)), dim3(256), 0, p->stream, (double*)(p->ws + p->lay.uf),
+                     p->ustar_cur, -1.0, n3);
+  HIPCHK(hipGetLastError());
+  p->ustar_cur = nullptr;
   return 0;
 }
 
@@ -1431,6 +1460,8 @@ int finish_step(fm_plan* p, const Ctrl& c, int t, bool last, fm_outputs* out, fm
     rc = set_outputs(p, nullptr);
     if (rc) return rc;
   }
+  rc = unfold_ustar(p);
+  if (rc) return rc;
   if (out && out->macro_sigma)
     for (int i = 0; i < 6; ++i) out->macro_sigma[t * 6 + i] = c.macro[i];
   if (out && out->iters) out->iters[t] = c.m;
@@ -1672,6 +1703,7 @@ int fm_set_material(fm_plan* p, const int32_t* d_mat_id, int32_t n_mat, const fm
     HIPCHK(hipMemsetAsync(ws + p->lay.sig, 0, R * 6 * p->g.nppv * (size_t)p->g.Nv, p->stream));
   }
   HIPCHK(hipStreamSynchronize(p->stream));
+  p->ustar_cur = nullptr;
   p->material_set = true;
   p->n_mat = n_mat;
   return FM_OK;
@@ -1752,6 +1784,12 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
   if (rc) return rc;
   const int64_t n3 = 3 * p->g.Nn;
   HIPCHK(hipMemcpyAsync(p->ws + p->lay.uf, d_uf, 8 * n3, hipMemcpyDeviceToDevice, p->stream));
+  if (step->ustar) {
+    hipLaunchKernelGGL(k_add_nodal, dim3(cdiv(n3, 256)), dim3(256), 0, p->stream, (double*)(p->ws + p->lay.uf),
+                       step->ustar, 1.0, n3);
+    HIPCHK(hipGetLastError());
+  }
+  p->ustar_cur = nullptr;    // the buffer is scratch here
   const Group& G = *p->self;
   hipStream_t st = p->stream;
   rc = p->d.prec == FM_FP64 ? launch_one<double>(G, 0) : launch_one<float>(G, 0);

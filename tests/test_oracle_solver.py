@@ -332,3 +332,59 @@ def test_finite_strain_small_load_limit(scheme):
     scale = np.abs(a).max()
     assert np.abs(a - b).max() < 1e-4 * scale
     assert np.abs(a - b).max() > 0
+
+
+def _nodal_poly(pl, step):
+    """The polynomial u* of a step as a nodal field (oracle layout)."""
+    return pl.ustar(step.c, step.G, step.H)
+
+
+@pytest.mark.parametrize("scheme", [W.HEX1, W.TETRA2])
+def test_ustar_interior_is_absorbed(scheme):
+    """Sec. 2.2 / Algorithm 1 set-up: u* enters only through its values on the
+    dismissed (Dirichlet) nodes of each component; a perturbation of a nodal
+    u* on the kept nodes is absorbed by u^f, so the strain and stress are
+    unchanged, and u = u^f + u* up to a mode of zero discrete strain (rigid
+    motions where the BCs leave them free, HEX1's hourglass modes: the null
+    modes of the Green operator).  A perturbation
+    on a Dirichlet face does change them."""
+    rng = np.random.default_rng(77 + scheme)
+    prob = W.random_small_problem(rng, n=(6, 5, 7), scheme=scheme, tol=1e-12)
+    pl = solver.Plan(prob)
+    base = solver.solve(prob)
+    pert = 1e-3 * rng.standard_normal((3,) + tuple(v + 1 for v in prob.n))
+    for q in range(3):
+        fd.zero_dismissed(pert[q], pl.exts[q])
+    p2 = W.random_small_problem(np.random.default_rng(77 + scheme), n=(6, 5, 7), scheme=scheme, tol=1e-12)
+    p2.steps[0].ustar_nodal = pert
+    r2 = solver.solve(p2)
+    scale = np.abs(base["sig"]).max()
+    np.testing.assert_allclose(r2["sig"], base["sig"], atol=1e-8 * scale)
+    np.testing.assert_allclose(r2["eps"], base["eps"], atol=1e-8 * np.abs(base["eps"]).max())
+    du = (r2["u"] - base["u"]).transpose(0, 3, 2, 1)
+    g = pl.grad(du)
+    assert np.abs(g + np.swapaxes(g, -1, -2)).max() < 1e-9 * np.abs(base["eps"]).max()
+    # the same perturbation on the dismissed nodes only moves the solution
+    dis = 1e-3 * rng.standard_normal(pert.shape)
+    mask = np.stack([~pl.kept[q] for q in range(3)])
+    if mask.any():
+        p3 = W.random_small_problem(np.random.default_rng(77 + scheme), n=(6, 5, 7), scheme=scheme, tol=1e-12)
+        p3.steps[0].ustar_nodal = np.where(mask, dis, 0.0)
+        r3 = solver.solve(p3)
+        assert np.abs(r3["sig"] - base["sig"]).max() > 1e-6 * scale
+
+
+def test_ustar_nodal_equals_polynomial():
+    """A nodal u* equal to the nodal values of the polynomial u* gives the
+    polynomial's solve (zero polynomial in its place)."""
+    rng = np.random.default_rng(5)
+    prob = W.random_small_problem(rng, n=(5, 6, 4), scheme=W.TETRA2, tol=1e-12, n_steps=2)
+    pl = solver.Plan(prob)
+    base = solver.solve(prob)
+    p2 = W.random_small_problem(np.random.default_rng(5), n=(5, 6, 4), scheme=W.TETRA2, tol=1e-12, n_steps=2)
+    for s in p2.steps:
+        s.ustar_nodal = _nodal_poly(pl, s)
+        s.c, s.G, s.H = np.zeros(3), np.zeros((3, 3)), np.zeros((3, 3, 3))
+    r2 = solver.solve(p2)
+    np.testing.assert_allclose(r2["sig"], base["sig"], atol=1e-9 * np.abs(base["sig"]).max())
+    np.testing.assert_allclose(r2["u"], base["u"], atol=1e-10 * np.abs(base["u"]).max())

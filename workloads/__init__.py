@@ -102,11 +102,15 @@ class LoadStep:
     # applied traction T*[axis i][face a][component q], uniform over the face
     # S_{i a}; non-zero only where u_q is Neumann on that face
     traction: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((3, 2, 3)))
+    # optional nodal field added to the polynomial u*: (3, N1, N2, N3), index
+    # [q, i, j, k] at node (i h, j h, k h)
+    ustar_nodal: Optional[np.ndarray] = None
 
     def copy(self) -> "LoadStep":
         return LoadStep(self.c.copy(), self.G.copy(), self.H.copy(),
                         self.mixed_mask.copy(), self.mixed_target.copy(), self.dt,
-                        self.traction.copy())
+                        self.traction.copy(),
+                        None if self.ustar_nodal is None else self.ustar_nodal.copy())
 
 
 def step_affine(G) -> LoadStep:
