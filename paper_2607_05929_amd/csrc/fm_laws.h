@@ -231,17 +231,23 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
     }
   }
   for (int it = 0; it < 80 && nr >= LawTol<R>::cp; ++it) {
-    R J[7][8];
+    // Newton matrix [[A, b], [c^T, d6]] on (sigma_M, dGamma): A = compliance +
+    // sum_s dt a_s P_s P_s^T is symmetric positive definite, so the step is a
+    // Cholesky solve of A against the residual and b, closed by the scalar
+    // Schur complement (no pivoting; the lower triangle of A only)
     const R hG = th0 * exp(-th0 * (Gn + dG) * ihs);
     const R itc = (R)1 / tc;
+    R A[6][6], bv[6], cv[6];
 #pragma unroll
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < 6; ++i) {
+      bv[i] = 0; cv[i] = 0;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) J[i][j] = 0;
-    J[0][0] = s11; J[1][1] = s11; J[2][2] = s11;
-    J[0][1] = J[1][0] = J[0][2] = J[2][0] = J[1][2] = J[2][1] = s12;
-    J[3][3] = s44; J[4][4] = s44; J[5][5] = s44;
-    J[6][6] = 1;
+      for (int j2 = 0; j2 <= i; ++j2) A[i][j2] = 0;
+    }
+    A[0][0] = s11; A[1][1] = s11; A[2][2] = s11;
+    A[1][0] = s12; A[2][0] = s12; A[2][1] = s12;
+    A[3][3] = s44; A[4][4] = s44; A[5][5] = s44;
+    R d6 = 1;
 #pragma unroll
     for (int s_ = 0; s_ < 12; ++s_) {
       const R r = tau_of(sig, s_) * itc;
@@ -254,46 +260,55 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
       for (int i = 0; i < 6; ++i) {
         const R pi = schmid_c<R>(s_, i);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) J[i][j] += ca * pi * schmid_c<R>(s_, j);
-        J[i][6] -= cb * pi;
-        J[6][i] -= cc * pi;
+        for (int j2 = 0; j2 <= i; ++j2) A[i][j2] += ca * pi * schmid_c<R>(s_, j2);
+        bv[i] -= cb * pi;
+        cv[i] -= cc * pi;
       }
-      J[6][6] += dt * nx * fabs(gs) * itc * hG;
+      d6 += dt * nx * fabs(gs) * itc * hG;
     }
+    bool spd = true;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) J[i][7] = Rs[i];
-    J[6][7] = Rg;
-    // Gaussian elimination, partial pivoting by compare-and-swap of the
-    // rows below the pivot (all indices compile-time: J stays in registers)
-    R ipv[7];
+    for (int j2 = 0; j2 < 6; ++j2) {
+      R dj = A[j2][j2];
 #pragma unroll
-    for (int p = 0; p < 7; ++p) {
+      for (int k = 0; k < j2; ++k) dj -= A[j2][k] * A[j2][k];
+      spd = spd && dj > 0;
+      const R ljj = sqrt(fmax(dj, (R)1e-300)), il = (R)1 / ljj;
+      A[j2][j2] = ljj;
 #pragma unroll
-      for (int q = p + 1; q < 7; ++q) {
-        const bool sw = fabs(J[q][p]) > fabs(J[p][p]);
+      for (int i = j2 + 1; i < 6; ++i) {
+        R t = A[i][j2];
 #pragma unroll
-        for (int c = p; c < 8; ++c) {
-          const R x = J[p][c], y = J[q][c];
-          J[p][c] = sw ? y : x;
-          J[q][c] = sw ? x : y;
-        }
-      }
-      ipv[p] = (R)1 / J[p][p];
-#pragma unroll
-      for (int q = p + 1; q < 7; ++q) {
-        const R f = J[q][p] * ipv[p];
-#pragma unroll
-        for (int c = p + 1; c < 8; ++c) J[q][c] -= f * J[p][c];
+        for (int k = 0; k < j2; ++k) t -= A[i][k] * A[j2][k];
+        A[i][j2] = t * il;
       }
     }
+    if (!spd) break;
+    // z1 = A^-1 Rs, z2 = A^-1 b (forward then backward substitution)
+    R z1[6], z2[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      R t1 = Rs[i], t2 = bv[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) { t1 -= A[i][k] * z1[k]; t2 -= A[i][k] * z2[k]; }
+      z1[i] = t1 / A[i][i];
+      z2[i] = t2 / A[i][i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+      R t1 = z1[i], t2 = z2[i];
+#pragma unroll
+      for (int k = i + 1; k < 6; ++k) { t1 -= A[k][i] * z1[k]; t2 -= A[k][i] * z2[k]; }
+      z1[i] = t1 / A[i][i];
+      z2[i] = t2 / A[i][i];
+    }
+    R cz1 = 0, cz2 = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) { cz1 += cv[i] * z1[i]; cz2 += cv[i] * z2[i]; }
     R dx[7];
+    dx[6] = (Rg - cz1) / (d6 - cz2);
 #pragma unroll
-    for (int p = 6; p >= 0; --p) {
-      R t = J[p][7];
-#pragma unroll
-      for (int c = p + 1; c < 7; ++c) t -= J[p][c] * dx[c];
-      dx[p] = t * ipv[p];
-    }
+    for (int i = 0; i < 6; ++i) dx[i] = z1[i] - z2[i] * dx[6];
     R lam = 1;
     R s_new[6], d_new, Rs2[6], Rg2, tc2, nr2 = nr;
     bool improved = false;

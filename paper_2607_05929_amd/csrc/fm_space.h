@@ -242,6 +242,11 @@ __global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* _
     const int law = gconst(s.mlaw)[mt];
     const FM_GLOBAL R* P = gconst((const R*)s.mtab) + (int64_t)mt * MT_STRIDE;
     for (int r = 0; r < s.nppv; ++r) {
+      // this point's strain by selects (a runtime index into eps would put
+      // the array in scratch memory)
+      E er[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) er[k] = r == 0 ? eps[0][k] : eps[1][k];
       R st[7], stn[7];
       FM_GLOBAL R* state = gmut((R*)s.state);
       if (PL && s.has_state) {
@@ -261,9 +266,9 @@ __global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* _
 #pragma unroll
           for (int k = 0; k < 6; ++k) sp[k] = gconst((const R*)s.sig)[((int64_t)k * s.nppv + r) * s.Nv + v];
         }
-        law_eval_e64<R>(law, P, eps[r], sig, st, stn, C->dt, warm ? sp : nullptr);
+        law_eval_e64<R>(law, P, er, sig, st, stn, C->dt, warm ? sp : nullptr);
       } else {
-        law_elastic<R>(law, P, eps[r], sig, st, stn);
+        law_elastic<R>(law, P, er, sig, st, stn);
       }
       if (SIGMA) {
 #pragma unroll
@@ -276,7 +281,7 @@ __global__ void __launch_bounds__(256, SIGMA ? 2 : 1) k_commit(const SolveDev* _
       }
       if (s.out_eps) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) gmut(s.out_eps)[((int64_t)k * s.nppv + r) * s.Nv + v] = (double)eps[r][k];
+        for (int k = 0; k < 6; ++k) gmut(s.out_eps)[((int64_t)k * s.nppv + r) * s.Nv + v] = (double)er[k];
       }
       if (s.out_sig) {
 #pragma unroll
