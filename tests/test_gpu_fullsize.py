@@ -109,3 +109,54 @@ def test_fullsize_sampled_equilibrium(runs, prec):
         worst = max(worst, float(np.abs(D).max()) * prob.h / s_rms)
     print(f"fullsize equilibrium prec={prec} max |D| h / sigma_rms = {worst:.2e}", flush=True)
     assert worst < 1e-4
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32_MIXED])
+def test_fullsize_sampled_equilibrium_on_faces(runs, prec):
+    """Equilibrium at sampled nodes on the traction-free y and z faces, their
+    edges and the corners they share, where the mirror rules act (the
+    x faces carry Dirichlet conditions: their nodes are dismissed): the
+    oracle's divergence of the GPU stress, with the problem's own extension
+    along the face normals, is negligible against the stress scale."""
+    from oracle import dt as odt
+    prob, out = runs
+    sig = out[prec]["sig"]
+    n1, n2, n3 = prob.n
+    bc = np.asarray(prob.bc)
+    rng = np.random.default_rng(13)
+    s_rms = np.sqrt(np.mean(np.sum(_tensor(sig[:, :, ::8, ::8, ::8].reshape(6, -1)) ** 2, axis=(-1, -2))))
+    cases = []
+    for _ in range(24):
+        x = int(rng.integers(1, n1))
+        y, z = int(rng.integers(1, n2)), int(rng.integers(1, n3))
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            y = int(rng.choice([0, n2]))
+        elif kind == 1:
+            z = int(rng.choice([0, n3]))
+        else:
+            y, z = int(rng.choice([0, n2])), int(rng.choice([0, n3]))
+        cases.append((x, y, z))
+    worst = 0.0
+    for x, y, z in cases:
+        # voxel patch around the node, clipped at the faces; the node's index in the patch
+        lo = [x - 1, max(y - 1, 0), max(z - 1, 0)]
+        hi = [x + 1, min(y + 1, n2), min(z + 1, n3)]
+        idx = [1, y - lo[1], z - lo[2]]
+        ext = []
+        for q in range(3):
+            e = [(odt.EXT_P, odt.EXT_P)]
+            for a, J, n in ((1, y, n2), (2, z, n3)):
+                if J in (0, n):   # the face's own extension on both sides of the (thin) patch
+                    side = odt.ext_of_bc(bc[q, a, 0 if J == 0 else 1])
+                    e.append((side, side))
+                else:
+                    e.append((odt.EXT_P, odt.EXT_P))
+            ext.append(e)
+        blk = sig[:, :, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        shp = blk.shape[2:]
+        S = _tensor(blk.reshape(6, -1)).reshape((sig.shape[1],) + shp + (3, 3)).transpose(0, 3, 2, 1, 4, 5)
+        D = fd.divergence(S, ext, prob.scheme, prob.h)[:, idx[0], idx[1], idx[2]]
+        worst = max(worst, float(np.abs(D).max()) * prob.h / s_rms)
+    print(f"fullsize face equilibrium prec={prec} max |D| h / sigma_rms = {worst:.2e}", flush=True)
+    assert worst < 1e-4
