@@ -1789,7 +1789,7 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
                        step->ustar, 1.0, n3);
     HIPCHK(hipGetLastError());
   }
-  p->ustar_cur = nullptr;    // the buffer is scratch here
+  p->ustar_cur = step->ustar;   // taken out again below: the buffer ends as d_uf
   const Group& G = *p->self;
   hipStream_t st = p->stream;
   rc = p->d.prec == FM_FP64 ? launch_one<double>(G, 0) : launch_one<float>(G, 0);
@@ -1808,6 +1808,8 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
   if (macro) for (int i = 0; i < 6; ++i) macro[i] = c.macro[i];
   c.status = ST_IDLE;
   HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+  rc = unfold_ustar(p);
+  if (rc) return rc;
   HIPCHK(hipStreamSynchronize(st));
   return FM_OK;
 }
@@ -1857,6 +1859,8 @@ int fm_profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, 
   for (int i = 0; i <= FM_N_KERNELS; ++i) HIPCHK(hipEventDestroy(ev[i]));
   c.status = ST_IDLE;
   HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+  rc = unfold_ustar(p);
+  if (rc) return rc;
   HIPCHK(hipStreamSynchronize(st));
   return FM_OK;
 }
