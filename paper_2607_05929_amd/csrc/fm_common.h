@@ -120,8 +120,10 @@ struct SolveDev {
   double* part_d;         // ntile_d
   double* part_g;         // ntile_d * NGRAM
   int32_t ntile_s, ntile_d;
-  int32_t sd_nt[3];       // stress-divergence tiles per axis
+  int32_t sd_nt[3];       // stress-divergence tiles per axis (x: full-width tiles only)
   int32_t sd_zc;          // node layers per stress-divergence tile
+  int32_t sd_tw;          // thread columns of the narrow x-remainder tiles
+  int32_t sd_tny;         // narrow x-remainder tiles per z slab (0: none)
   int32_t wrap[3];        // axis periodic for some component
   int32_t mixed_wrap;     // some axis periodic for some components only
   double* out_u;

@@ -70,7 +70,8 @@ struct Geometry {
   int U[3];          // C0: frequencies per axis shared by the components
   int ntile_c0;      // C0: tiles of the coupled apply
   int wrap[3];       // axis periodic for some component (halo voxels take the periodic image)
-  int sd_nt[3];      // fused stress-divergence tiles per axis
+  int sd_nt[3];      // fused stress-divergence tiles per axis (x: full-width tiles only)
+  int sd_tw, sd_tny; // narrow x-remainder tiles: thread columns, tiles per z slab (0: none)
   int sd_zc;         // node layers per fused stress-divergence tile
   int ntile_s;       // fused stress-divergence tiles
   int ntile_v;       // voxel tiles (commit)
@@ -217,8 +218,16 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
     g.wrap[i] = 0;
     for (int q = 0; q < 3; ++q) g.wrap[i] |= g.kinds[q][i] == K_DFT ? 1 : 0;
   }
-  g.sd_nt[0] = (int)cdiv(g.N[0], SD_TX);
+  // 31-node x tiles; the remainder takes narrow tiles of its own width
+  // (rem + 1 thread columns, SD_VT / (rem + 1) rows)
+  g.sd_nt[0] = g.N[0] / SD_TX;
   g.sd_nt[1] = (int)cdiv(g.N[1], SD_TY);
+  {
+    const int rem = g.N[0] - g.sd_nt[0] * SD_TX;
+    g.sd_tw = rem > 0 ? rem + 1 : 32;
+    g.sd_tny = rem > 0 ? (int)cdiv(g.N[1], SD_VT / g.sd_tw - 1) : 0;
+  }
+  const int64_t sd_per_slab = (int64_t)g.sd_nt[0] * g.sd_nt[1] + g.sd_tny;
   // Layers per tile: at most SD_ZC, the node layers split evenly over the
   // z tiles; the number of z tiles doubles while the grid gives fewer than
   // 8 blocks per compute unit.  Each tile recomputes one voxel layer below
@@ -228,10 +237,10 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   // block that still pays for its halo layer.
   const int64_t want = SD_WANT_BLOCKS;
   int64_t nzt = cdiv(g.N[2], SD_ZC);
-  while (nzt < g.N[2] && (int64_t)g.sd_nt[0] * g.sd_nt[1] * nzt < want) nzt = std::min<int64_t>(2 * nzt, g.N[2]);
+  while (nzt < g.N[2] && sd_per_slab * nzt < want) nzt = std::min<int64_t>(2 * nzt, g.N[2]);
   g.sd_zc = (int)cdiv(g.N[2], nzt);
   g.sd_nt[2] = (int)cdiv(g.N[2], g.sd_zc);
-  g.ntile_s = g.sd_nt[0] * g.sd_nt[1] * g.sd_nt[2];
+  g.ntile_s = (int)(sd_per_slab * g.sd_nt[2]);
   g.ntile_v = (int)cdiv(g.Nv, SPACE_TILE);
   g.ntile_d = (int)cdiv(g.Nn, SPACE_TILE);
   g.ntile_c0 = 0;
@@ -289,7 +298,7 @@ inline SdivTiling sdiv_tiling(const Geometry& g, bool deep) {
   const int64_t nzt = cdiv(g.N[2], SD_ZC);
   const int zc = std::max(g.sd_zc, (int)cdiv(g.N[2], nzt));
   const int nz = (int)cdiv(g.N[2], zc);
-  return {zc, nz, g.sd_nt[0] * g.sd_nt[1] * nz};
+  return {zc, nz, (g.sd_nt[0] * g.sd_nt[1] + g.sd_tny) * nz};
 }
 
 void tiles_of(const Geometry& g, int64_t t[NWL]) {
@@ -1615,6 +1624,8 @@ int fm_plan_create(const fm_plan_desc* desc, void* d_workspace, size_t ws_bytes,
   for (int i = 0; i < 3; ++i) {
     s.sd_nt[i] = g.sd_nt[i];
     s.sd_zc = g.sd_zc;
+    s.sd_tw = g.sd_tw;
+    s.sd_tny = g.sd_tny;
     s.wrap[i] = g.wrap[i];
     for (int q = 0; q < 3; ++q)
       if (g.wrap[i] && g.kinds[q][i] != K_DFT) s.mixed_wrap = 1;

@@ -142,9 +142,9 @@ __global__ void __launch_bounds__(256) k_fs_div(const SolveDev* __restrict__ S, 
   const SolveDev& s = S[w.x];
   const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
   if (C->status != ST_RUNNING) return;
-  const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
-  const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * s.sd_zc;
-  const int X1 = min(X0 + SD_TX, s.N[0]), Y1 = min(Y0 + SD_TY, s.N[1]), Z1 = min(Z0 + s.sd_zc, s.N[2]);
+  const SdBox bx = sd_box(s, w.y);
+  const int X0 = bx.X0, Y0 = bx.Y0, Z0 = bx.Z0;
+  const int X1 = min(X0 + bx.W - 1, s.N[0]), Y1 = min(Y0 + bx.H - 1, s.N[1]), Z1 = min(Z0 + s.sd_zc, s.N[2]);
   const int nx = X1 - X0, ny = Y1 - Y0, nz = Z1 - Z0;
   const int n[3] = {s.n[0], s.n[1], s.n[2]};
   const FM_GLOBAL double* Sg = gconst((const double*)s.sig);

@@ -313,6 +313,33 @@ constexpr int SD_TX = 31, SD_TY = 7, SD_ZC = 32;   // node tile (at most SD_ZC l
 constexpr int SD_VT = 256;                          // voxels per layer tile
 constexpr int SD_WANT_BLOCKS = 8 * 256;             // stress-divergence tiles that fill the GPU
 
+// Thread box of stress-divergence tile idx: W x H threads over the voxel
+// columns of the tile and its one-voxel halo, (W - 1) x (H - 1) node columns
+// from (X0, Y0), node layers from Z0.  The x range is cut into 31-node
+// tiles; the remainder (fewer than 31 nodes) gets tiles of its own width
+// and SD_VT / W rows, so that its threads are not mostly idle.  Threads past
+// W x H (SD_VT not a multiple of W) own no voxel and no node.
+struct SdBox {
+  int X0, Y0, Z0, W, H;
+};
+__device__ __forceinline__ SdBox sd_box(const SolveDev& s, int idx) {
+  const int full = s.sd_nt[0] * s.sd_nt[1];
+  const int per = full + s.sd_tny;
+  const int z = idx / per, r = idx - z * per;
+  SdBox b;
+  b.Z0 = z * s.sd_zc;
+  if (r < full) {
+    b.W = 32; b.H = 8;
+    b.X0 = (r % s.sd_nt[0]) * SD_TX;
+    b.Y0 = (r / s.sd_nt[0]) * SD_TY;
+  } else {
+    b.W = s.sd_tw; b.H = SD_VT / s.sd_tw;
+    b.X0 = s.sd_nt[0] * SD_TX;
+    b.Y0 = (r - full) * (b.H - 1);
+  }
+  return b;
+}
+
 __device__ __forceinline__ int map_vox(int g, int n, int wrap) {
   if (g < 0) return wrap ? n - 1 : 0;
   if (g >= n) return wrap ? min(g - n, n - 1) : n - 1;
@@ -444,7 +471,7 @@ __device__ __forceinline__ NodeXY<R> node_xy(const SolveDev& s, int J0, int J1) 
 // a reflecting z face, 0 where not kept along z) from the column partials of
 // its four voxel columns; D written through Dn (this node in component 0).
 template <typename CT, typename R, int TR, bool DROP>
-__device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int ly, const NodeXY<CT>& nxy,
+__device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int ly, int TW, const NodeXY<CT>& nxy,
                                          const CT (&fz)[3], FM_GLOBAL R* Dn, int64_t Nn, CT& accD,
                                          const SolveDev& s, const FM_GLOBAL Ctrl* C, int J0, int J1, int J2) {
 #pragma unroll
@@ -454,7 +481,7 @@ __device__ __forceinline__ void node_div(const CT* __restrict__ P, int lx, int l
     for (int b1 = 0; b1 < 2; ++b1)
 #pragma unroll
       for (int b0 = 0; b0 < 2; ++b0) {
-        const CT t = P[(q * 4 + b1 * 2 + b0) * SD_VT + (ly + b1) * 32 + (lx + b0)];
+        const CT t = P[(q * 4 + b1 * 2 + b0) * SD_VT + (ly + b1) * TW + (lx + b0)];
         if constexpr (DROP) D += ((nxy.drop >> (q * 4 + b1 * 2 + b0)) & 1) ? (CT)0 : t;
         else D += t;
       }
@@ -484,17 +511,17 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
   if (sizeof(R) == 4 && (C->rs64 != 0) != (sizeof(CT) == 8)) return;
   extern __shared__ __align__(16) char smem[];
   CT* sl = (CT*)smem;                                  // column partials [2][12][SD_VT]
-  const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
-  const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * s.sd_zc;
+  const SdBox bx = sd_box(s, w.y);
+  const int X0 = bx.X0, Y0 = bx.Y0, Z0 = bx.Z0, TW = bx.W;
   const int Z1 = min(Z0 + s.sd_zc, s.N[2]);
-  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  const int lx = (int)threadIdx.x % TW, ly = (int)threadIdx.x / TW;
   const int n0 = s.n[0], n1 = s.n[1], n2 = s.n[2];
   const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
   const int vx = map_vox(gx, n0, s.wrap[0]), vy = map_vox(gy, n1, s.wrap[1]);
-  const bool own_xy = lx >= 1 && ly >= 1 && gx < n0 && gy < n1;
+  const bool own_xy = lx >= 1 && ly >= 1 && ly < bx.H && gx < n0 && gy < n1;
   const bool zero_xy = (!s.wrap[0] && (gx < 0 || gx >= n0)) || (!s.wrap[1] && (gy < 0 || gy >= n1));
   const int J0 = X0 + lx, J1 = Y0 + ly;
-  const bool has_node = lx < SD_TX && ly < SD_TY && J0 < s.N[0] && J1 < s.N[1];
+  const bool has_node = lx < TW - 1 && ly < bx.H - 1 && J0 < s.N[0] && J1 < s.N[1];
   const FM_GLOBAL uint16_t* mat = gconst(s.mat);
   const CT wip = (CT)1 / (CT)s.nppv;
   // per-thread partials in CT (each thread sums at most 2 (sd_zc + 1) points),
@@ -657,10 +684,10 @@ __device__ __forceinline__ void sdiv_tile(const SolveDev* __restrict__ S, const 
       __syncthreads();
       if (has_node) {
         if (wave_drop)
-          node_div<CT, R, TR, true>(slb, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
+          node_div<CT, R, TR, true>(slb, lx, ly, TW, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
                                     Y0 + ly, zl);
         else
-          node_div<CT, R, TR, false>(slb, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
+          node_div<CT, R, TR, false>(slb, lx, ly, TW, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
                                      Y0 + ly, zl);
       }
     }
@@ -697,17 +724,17 @@ __device__ __forceinline__ void sdiv_tile_f32(const SolveDev* __restrict__ S, co
   if (C->rs64 != 0) return;
   extern __shared__ __align__(16) char smem[];
   CT* sl = (CT*)smem;                                  // column partials [2][12][SD_VT]
-  const int ntx = s.sd_nt[0], nty = s.sd_nt[1];
-  const int X0 = (w.y % ntx) * SD_TX, Y0 = ((w.y / ntx) % nty) * SD_TY, Z0 = (w.y / (ntx * nty)) * s.sd_zc;
+  const SdBox bx = sd_box(s, w.y);
+  const int X0 = bx.X0, Y0 = bx.Y0, Z0 = bx.Z0, TW = bx.W;
   const int Z1 = min(Z0 + s.sd_zc, s.N[2]);
-  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  const int lx = (int)threadIdx.x % TW, ly = (int)threadIdx.x / TW;
   const int n0 = s.n[0], n1 = s.n[1], n2 = s.n[2];
   const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
   const int vx = map_vox(gx, n0, s.wrap[0]), vy = map_vox(gy, n1, s.wrap[1]);
-  const bool own_xy = lx >= 1 && ly >= 1 && gx < n0 && gy < n1;
+  const bool own_xy = lx >= 1 && ly >= 1 && ly < bx.H && gx < n0 && gy < n1;
   const bool zero_xy = (!s.wrap[0] && (gx < 0 || gx >= n0)) || (!s.wrap[1] && (gy < 0 || gy >= n1));
   const int J0 = X0 + lx, J1 = Y0 + ly;
-  const bool has_node = lx < SD_TX && ly < SD_TY && J0 < s.N[0] && J1 < s.N[1];
+  const bool has_node = lx < TW - 1 && ly < bx.H - 1 && J0 < s.N[0] && J1 < s.N[1];
   const FM_GLOBAL uint16_t* mat = gconst(s.mat);
   const FM_GLOBAL int* mlaw = gconst(s.mlaw);
   const FM_GLOBAL R* mtab = gconst((const R*)s.mtab);
@@ -849,10 +876,10 @@ __device__ __forceinline__ void sdiv_tile_f32(const SolveDev* __restrict__ S, co
       __syncthreads();
       if (has_node) {
         if (wave_drop)
-          node_div<CT, R, TR, true>(slb, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
+          node_div<CT, R, TR, true>(slb, lx, ly, TW, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
                                     Y0 + ly, zl);
         else
-          node_div<CT, R, TR, false>(slb, lx, ly, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
+          node_div<CT, R, TR, false>(slb, lx, ly, TW, nxy, fz, Dcol + (int64_t)zl * N01, s.Nn, acc[7], s, C, X0 + lx,
                                      Y0 + ly, zl);
       }
     }
