@@ -368,31 +368,6 @@ __device__ __forceinline__ void law_elastic(int law, PT P, const R eps[6], R sig
   for (int i = 0; i < 7; ++i) stn[i] = st[i];
 }
 
-// Elastic stresses of the first NP integration points of a voxel (same
-// arithmetic as law_elastic, one law branch for all points).
-template <typename R, int NP, typename PT>
-__device__ __forceinline__ void law_elastic_pts(int law, PT P, const R (&eps)[2][6], R (&sig)[2][6]) {
-  if (law == LAW_ISO) {
-    const R lam = P[0], mu = P[1];
-#pragma unroll
-    for (int r = 0; r < NP; ++r) {
-      const R tr = eps[r][0] + eps[r][1] + eps[r][2];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) sig[r][i] = 2 * mu * eps[r][i] + lam * tr;
-#pragma unroll
-      for (int i = 3; i < 6; ++i) sig[r][i] = 2 * mu * eps[r][i];
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < NP; ++r) {
-      R em[6], sm[6];
-      to_mandel(eps[r], em);
-      mat6sym<R>(P, em, sm);
-      from_mandel(sm, sig[r]);
-    }
-  }
-}
-
 // Elastic laws with engineering shear strains (eps[3..5] twice the tensor
 // components), as the fused real-space kernel forms them, from the entry's
 // Voigt stiffness c (packed upper triangle, stored at MT_VOIGT; no Mandel
