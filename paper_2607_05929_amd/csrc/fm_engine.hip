@@ -53,6 +53,20 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // ---------------------------------------------------------------------------
 // Geometry of one solve
 // ---------------------------------------------------------------------------
+// Wavefront kernel for a pencil of length L: 64 lanes with E = L / 64 (E as
+// in wave_E_ok), else 32 or 16 lanes per pencil with E = L / LN in {1, 3}
+// (L = 16, 32, 48, 96); returns E and sets LN, or 0 when none applies.
+inline int wave_shape(int L, int& LN) {
+  LN = 64;
+  if (L % 64 == 0 && wave_E_ok(L / 64)) return L / 64;
+  for (int ln = 32; ln >= 16; ln /= 2)
+    if (L % ln == 0 && (L / ln == 1 || L / ln == 3)) { LN = ln; return L / ln; }
+  return 0;
+}
+// Tile width of the wavefront kernels: two real columns per pencil (packed)
+// or one complex column, 8 wavefronts of 64 / LN pencils.
+inline int wave_cols(int LN, bool packed) { return (packed ? 2 : 1) * WAVE_PENCILS * (64 / LN); }
+
 struct Geometry {
   int n[3], N[3];
   int64_t Nn, Nv;
@@ -63,7 +77,8 @@ struct Geometry {
   int64_t s1[3], s2[3];   // reals of stage-1 / stage-2 buffers per component
   int L[3][3];
   int F[3][7];       // FFTs per block per pass slot (generic kernel)
-  int wE[3][7];      // wavefront kernel E = L / 64 per pass slot, 0 = generic kernel
+  int wE[3][7];      // wavefront kernel E = L / wN per pass slot, 0 = generic kernel
+  int wN[3][7];      // lanes per pencil of that kernel: 64, or 32 / 16 (two / four pencils per wavefront)
   int cols[3][7];    // columns (or rows) per block per pass slot
   int c0;            // C0 Green operator: z pass split (slots 5, 6) around the coupled apply
   int64_t s3[3];     // reals of the z-spectral buffer per component (C0 only)
@@ -189,25 +204,27 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
     for (int pass = 5; pass < 7; ++pass) {
       g.F[q][pass] = g.F[q][2];
       g.wE[q][pass] = 0;
+      g.wN[q][pass] = 64;
       g.cols[q][pass] = !g.cplx[q][1] ? 2 * g.F[q][pass] : g.F[q][pass];
     }
     for (int pass = 0; pass < 5; ++pass) {
       const int axis = pass == 0 || pass == 4 ? 0 : (pass == 2 ? 2 : 1);
       const int L = g.L[q][axis];
       const bool packed = axis == 0 ? true : !g.cplx[q][axis - 1];
-      const int E = L % 64 == 0 ? L / 64 : 0;
+      int LN;
+      const int E = wave_shape(L, LN);
       // wavefront kernels address a component's buffers with 32-bit byte offsets
       const int64_t comp_bytes = std::max(std::max(g.s1[q], g.s2[q]) * (int64_t)g.rbytes, g.Nn * (int64_t)8);
-      g.wE[q][pass] = (E && wave_E_ok(E) && comp_bytes < ((int64_t)1 << 32)) ? E : 0;
+      g.wE[q][pass] = (E && comp_bytes < ((int64_t)1 << 32)) ? E : 0;
+      g.wN[q][pass] = E ? LN : 64;
       if (g.wE[q][pass]) {
         // wavefront kernel staging (bounded as in build_group) must fit the LDS
-        const int cols = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
         const size_t rows = (size_t)g.n[axis] + 3;
-        size_t bytes = rows * (cols + 1) * 2 * (size_t)g.rbytes;
+        size_t bytes = rows * (wave_cols(LN, packed) + 1) * 2 * (size_t)g.rbytes;
         if (E == 8) bytes += (size_t)WAVE_PENCILS * WT_SIZE * g.rbytes;
         if (bytes > 150 * 1024) g.wE[q][pass] = 0;
       }
-      if (g.wE[q][pass]) g.cols[q][pass] = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
+      if (g.wE[q][pass]) g.cols[q][pass] = wave_cols(LN, packed);
       else g.cols[q][pass] = packed ? 2 * g.F[q][pass] : g.F[q][pass];
       if (!g.wE[q][pass] && (generic_radix(L) ? 2 : 1) * (size_t)g.F[q][pass] * pencil_stride(L) * 2 * g.rbytes >
                                 160 * 1024 - 2048)
@@ -534,15 +551,17 @@ struct fm_plan {
 
 // A set of solves advanced together.
 // Pass kernel variants: generic (0), wavefront E = 1,2,3,4,5,6,12,16 (1-9,
-// 7 unused), and for E = 8 one bucket per transform kind and packing
-// (10 + 2 kind + packed), whose kernels fix both at compile time.
-constexpr int NBUCKET = 20;
-inline int bucket_of(int E, int kind, int packed) {
+// 7 unused), for E = 8 one bucket per transform kind and packing
+// (10 + 2 kind + packed), whose kernels fix both at compile time, and the
+// 32- and 16-lane pencils with E = 1 and 3 (20-23).
+constexpr int NBUCKET = 24;
+inline int bucket_of(int E, int LN, int kind, int packed) {
+  if (E && LN != 64) return 20 + (LN == 16 ? 2 : 0) + (E == 3 ? 1 : 0);
   switch (E) { case 1: return 1; case 2: return 2; case 3: return 3; case 4: return 4; case 5: return 5;
                case 6: return 6; case 8: return 10 + 2 * kind + (packed ? 1 : 0); case 12: return 8;
                case 16: return 9; default: return 0; }
 }
-constexpr int E_of_bucket[NBUCKET] = {0, 1, 2, 3, 4, 5, 6, 8, 12, 16, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8};
+constexpr int E_of_bucket[NBUCKET] = {0, 1, 2, 3, 4, 5, 6, 8, 12, 16, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 1, 3, 1, 3};
 
 struct Group {
   int prec = 0;
@@ -869,9 +888,9 @@ int build_group(Group& G, fm_plan* const* plans, int ns, char* dev, size_t bytes
         if (!slot_used(p->g, pass)) continue;
         const int64_t ntiles = pass == 0 || pass == 4 ? d.tiles_p0 : (int64_t)d.tiles_p0 * d.n_p1;
         const int pk = pass;   // launch order slot
-        const int E = p->g.wE[q][pass];
-        const int b = bucket_of(E, d.kind, d.packed);
-        if (E == 8 && (d.cols != (d.packed ? 2 * WAVE_PENCILS : WAVE_PENCILS) || d.L != 512))
+        const int E = p->g.wE[q][pass], LN = p->g.wN[q][pass];
+        const int b = bucket_of(E, LN, d.kind, d.packed);
+        if (E && (d.cols != wave_cols(LN, d.packed) || d.L != LN * E))
           return fail(FM_E_INVALID_ARG, "internal: wavefront pass descriptor does not match its kernel");
         for (int64_t ty = 0; ty < ntiles; ++ty) pb[pk][b].push_back(make_int2(di, (int)ty));
         size_t lds;
@@ -1151,7 +1170,14 @@ int launch_bucket(const Group& G, int pk, int b) {
   const dim3 grid((unsigned)G.bn[pk][b]);
   const size_t lds = G.blds[pk][b];
   hipStream_t st = G.stream;
-  if (b >= 10) {
+  if (b >= 20) {
+    switch (b) {
+      case 20: hipLaunchKernelGGL((k_wave<R, MODE, XP, 1, -1, -1, 32>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+      case 21: hipLaunchKernelGGL((k_wave<R, MODE, XP, 3, -1, -1, 32>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+      case 22: hipLaunchKernelGGL((k_wave<R, MODE, XP, 1, -1, -1, 16>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+      default: hipLaunchKernelGGL((k_wave<R, MODE, XP, 3, -1, -1, 16>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
+    }
+  } else if (b >= 10) {
     launch_w8_kind<R, MODE, XP>((b - 10) >> 1, (b - 10) & 1, grid, lds, st, G.P, wl, G.S);
   } else switch (E_of_bucket[b]) {
     case 0: hipLaunchKernelGGL((k_pass<R, MODE, XP>), grid, dim3(PASS_THREADS), lds, st, G.P, wl, G.S); break;
@@ -1519,7 +1545,8 @@ int read_ctrl(fm_plan* p, Ctrl& c) {
 // Transform-kernel autotuning
 // ---------------------------------------------------------------------------
 // Candidates for one pass index (all three components): 0 = wavefront kernel
-// (pencil length 64E), 1..3 = generic LDS kernel with F = Fmax, Fmax/2,
+// (pencil length 64E, or 32E / 16E for E in {1, 3}), 1..3 = generic LDS
+// kernel with F = Fmax, Fmax/2,
 // Fmax/4 transforms per block.  Returns false when the candidate does not
 // apply to some component (the pass then keeps its current kernel).
 constexpr int N_TUNE = 4;
@@ -1531,14 +1558,16 @@ bool apply_choice(Geometry& g, int pass, int choice) {
     const int L = h.L[q][axis];
     const bool packed = axis == 0 ? true : !h.cplx[q][axis - 1];
     if (choice == 0) {
-      const int E = L % 64 == 0 ? L / 64 : 0;
-      if (!E || !wave_E_ok(E)) return false;
+      int LN;
+      const int E = wave_shape(L, LN);
+      if (!E) return false;
       if (std::max(std::max(h.s1[q], h.s2[q]) * (int64_t)h.rbytes, h.Nn * (int64_t)8) >= ((int64_t)1 << 32)) return false;
-      const int cols = packed ? 2 * WAVE_PENCILS : WAVE_PENCILS;
+      const int cols = wave_cols(LN, packed);
       size_t bytes = ((size_t)h.n[axis] + 3) * (cols + 1) * 2 * (size_t)h.rbytes;
       if (E == 8) bytes += (size_t)WAVE_PENCILS * WT_SIZE * h.rbytes;
       if (bytes > 150 * 1024) return false;
       h.wE[q][pass] = E;
+      h.wN[q][pass] = LN;
       h.cols[q][pass] = cols;
     } else {
       const int Fmax = choose_F(L, h.rbytes, 16);

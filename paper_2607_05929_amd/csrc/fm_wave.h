@@ -1,15 +1,20 @@
 // Wavefront-per-pencil axis passes for pencil lengths L = 64 E (E in
-// {1, 2, 3, 4, 5, 6, 8, 12, 16}), the common case of the solver's grids.
+// {1, 2, 3, 4, 5, 6, 8, 12, 16}), the common case of the solver's grids,
+// and half- / quarter-wavefront forms for L = 32 E and 16 E (E in {1, 3}):
+// LN = 32 or 16 lanes per pencil, two or four pencils per wavefront, so
+// that the 32-, 48- and 96-point pencils of small grids also take the
+// register transform instead of the generic LDS kernel.
 //
-// A block of 8 wavefronts owns a tile of 8 pencils (16 real columns packed
-// two per pencil, or 8 complex columns): small blocks so that several fit a
+// A block of 8 wavefronts owns a tile of 8 (64 / LN) pencils (16 real columns
+// packed two per pencil, or 8 complex columns, per 64 lanes per pencil):
+// small blocks so that several fit a
 // compute unit and one block's loads overlap another's arithmetic.  The tile
 // is loaded with coalesced 64-byte row segments (whole rows along x) into an
 // LDS staging array; each wavefront then gathers its pencil's virtual
 // extension (Table 1) straight into registers, lane t holding positions
-// t + 64 j (j < E), and transforms it with
-//   X[k1 + E k2] = sum_t W_L^{t k1} W_64^{t k2} sum_j x[t + 64 j] W_E^{j k1}:
-// an E-point DFT in registers, a twiddle, and a 64-point DFT across the
+// t + LN j (j < E), and transforms it with
+//   X[k1 + E k2] = sum_t W_L^{t k1} W_LN^{t k2} sum_j x[t + LN j] W_E^{j k1}:
+// an E-point DFT in registers, a twiddle, and an LN-point DFT across the
 // lanes (radix-2 butterflies through lane exchanges, decimation in frequency
 // forward and in time inverse, so the spectrum stays in bit-reversed lane
 // order and needs no reordering).  The Green operator of the fused z pass
@@ -40,59 +45,71 @@ __device__ __forceinline__ cx<R> shfl_c(cx<R> v, int src) {
 
 __device__ __forceinline__ int brev6(int x) { return (int)(__brev((unsigned)x) >> 26); }
 
-// Per-lane constants of the 64-point lane DFT.  Stage i pairs lanes that
-// differ in bit h = 32 >> i; sg[i] is +1 on the lane with the bit clear and
-// -1 on the lane with it set, s[i] is W_{2h}^{lane mod h} on the lane with the
-// bit set and 1 on the other (forward values; the inverse uses conjugates).
-// They depend on the lane only and are loaded once per pencil pass.
-template <typename R>
+constexpr int lanes_log2(int LN) { return LN == 64 ? 6 : LN == 32 ? 5 : 4; }
+
+// Bit reversal of an LN-lane index.
+template <int LN>
+__device__ __forceinline__ int brev_ln(int x) { return (int)(__brev((unsigned)x) >> (32 - lanes_log2(LN))); }
+
+// Per-lane constants of the LN-point lane DFT (stages ST = log2 LN).  Stage i
+// pairs lanes that differ in bit h = LN / 2 >> i; sg[i] is +1 on the lane
+// with the bit clear and -1 on the lane with it set, s[i] is W_{2h}^{lane mod
+// h} on the lane with the bit set and 1 on the other (forward values; the
+// inverse uses conjugates).  They depend on the lane only and are loaded once
+// per pencil pass.
+template <typename R, int LN = 64>
 struct LaneTw {
-  cx<R> s[5];
-  R sg[6];
+  static constexpr int ST = lanes_log2(LN);
+  cx<R> s[ST - 1];
+  R sg[ST];
 };
 
-template <typename R>
-__device__ __forceinline__ LaneTw<R> lane_twiddles(const FM_GLOBAL cx<R>* W, int L) {
-  const int lane = threadIdx.x & 63;
-  LaneTw<R> tw;
+template <typename R, int LN>
+__device__ __forceinline__ LaneTw<R, LN> lane_twiddles(const FM_GLOBAL cx<R>* W, int L) {
+  constexpr int ST = lanes_log2(LN);
+  const int lane = threadIdx.x & (LN - 1);
+  LaneTw<R, LN> tw;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const int h = 32 >> i;
+  for (int i = 0; i < ST; ++i) {
+    const int h = (LN / 2) >> i;
     tw.sg[i] = (lane & h) ? (R)-1 : (R)1;
-    if (i < 5) tw.s[i] = (lane & h) ? twid<R>(W, (lane & (h - 1)) * (L / (2 * h)), false) : mk<R>(1, 0);
+    if (i < ST - 1) tw.s[i] = (lane & h) ? twid<R>(W, (lane & (h - 1)) * (L / (2 * h)), false) : mk<R>(1, 0);
   }
   return tw;
 }
 
-// Forward 64-point DFT across the lanes of every register, decimation in
-// frequency: lane t starts with x[t] and ends with X[brev6(t)].  Stages are
-// the outer loop so that the exchanges of all registers are in flight
-// together; the butterflies are branch free (sign and twiddle per lane).
-template <typename R, int E>
-__device__ __forceinline__ void lane_dif64(cx<R> (&v)[E], const LaneTw<R>& tw) {
+// Forward LN-point DFT across the lanes of every register (each group of LN
+// lanes on its own), decimation in frequency: lane t starts with x[t] and
+// ends with X[brev(t)].  Stages are the outer loop so that the exchanges of
+// all registers are in flight together; the butterflies are branch free
+// (sign and twiddle per lane).
+template <typename R, int E, int LN>
+__device__ __forceinline__ void lane_dif(cx<R> (&v)[E], const LaneTw<R, LN>& tw) {
+  constexpr int ST = lanes_log2(LN);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const int h = 32 >> i;
+  for (int i = 0; i < ST; ++i) {
+    const int h = (LN / 2) >> i;
     cx<R> pv[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) pv[k] = shfl_xor_c(v[k], h);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       cx<R> z = mk<R>(fma(tw.sg[i], v[k].re, pv[k].re), fma(tw.sg[i], v[k].im, pv[k].im));
-      if (i < 5) z = mul(z, tw.s[i]);
+      if (i < ST - 1) z = mul(z, tw.s[i]);
       v[k] = z;
     }
   }
 }
 
-// Inverse 64-point DFT across the lanes (unnormalised), decimation in time:
-// lane t starts with X[brev6(t)] and ends with x[t].
-template <typename R, int E>
-__device__ __forceinline__ void lane_dit64(cx<R> (&v)[E], const LaneTw<R>& tw) {
+// Inverse LN-point DFT across the lanes (unnormalised), decimation in time:
+// lane t starts with X[brev(t)] and ends with x[t].
+template <typename R, int E, int LN>
+__device__ __forceinline__ void lane_dit(cx<R> (&v)[E], const LaneTw<R, LN>& tw) {
+  constexpr int ST = lanes_log2(LN);
 #pragma unroll
-  for (int i = 5; i >= 0; --i) {
-    const int h = 32 >> i;
-    if (i < 5) {
+  for (int i = ST - 1; i >= 0; --i) {
+    const int h = (LN / 2) >> i;
+    if (i < ST - 1) {
 #pragma unroll
       for (int k = 0; k < E; ++k) v[k] = mul(v[k], conj(tw.s[i]));
     }
@@ -149,20 +166,21 @@ __device__ __forceinline__ void dft_reg(cx<R> (&v)[E], const FM_GLOBAL cx<R>* W,
   }
 }
 
-// Forward: lane t holds x[t + 64 j] in v[j]; on return lane t holds
-// X[k1 + E brev6(t)] in v[k1].  Inverse: the exact mirror image (input in
-// that bit-reversed layout, output x[t + 64 j] in v[j], unnormalised).
-template <typename R, int E>
-__device__ __forceinline__ void wave_fft(cx<R> (&v)[E], const FM_GLOBAL cx<R>* W, const LaneTw<R>& tw, bool inv) {
-  constexpr int L = 64 * E;
-  const int t = threadIdx.x & 63;
+// Forward: lane t (of LN) holds x[t + LN j] in v[j]; on return lane t holds
+// X[k1 + E brev(t)] in v[k1].  Inverse: the exact mirror image (input in
+// that bit-reversed layout, output x[t + LN j] in v[j], unnormalised).
+template <typename R, int E, int LN>
+__device__ __forceinline__ void wave_fft(cx<R> (&v)[E], const FM_GLOBAL cx<R>* W, const LaneTw<R, LN>& tw,
+                                         bool inv) {
+  constexpr int L = LN * E;
+  const int t = threadIdx.x & (LN - 1);
   if (!inv) {
     dft_reg<R, E>(v, W, L, false);
 #pragma unroll
     for (int k1 = 1; k1 < E; ++k1) v[k1] = mul(v[k1], twid<R>(W, t * k1, false));
-    lane_dif64<R, E>(v, tw);
+    lane_dif<R, E, LN>(v, tw);
   } else {
-    lane_dit64<R, E>(v, tw);
+    lane_dit<R, E, LN>(v, tw);
 #pragma unroll
     for (int k1 = 1; k1 < E; ++k1) v[k1] = mul(v[k1], twid<R>(W, t * k1, true));
     dft_reg<R, E>(v, W, L, true);
@@ -258,24 +276,28 @@ __device__ __forceinline__ void wave_fft8(cx<R> (&v)[8], const TW& W, R* sb, boo
   }
 }
 
-// Spectral index held by register r of lane t after a forward transform.
-template <int E>
+// Spectral index held by register r of lane t (of LN) after a forward
+// transform.
+template <int E, int LN = 64>
 __device__ __forceinline__ int spec_pos(int t, int r) {
   if constexpr (E == 8) return (t >> 3) + 8 * (t & 7) + 64 * r;
-  else return r + E * brev6(t);
+  else return r + E * brev_ln<LN>(t);
 }
 
 // Value of the partner position L - m of register r (lane t holds
-// m = spec_pos<E>(t, r)).  Lane exchange only; every lane takes part.
+// m = spec_pos<E, LN>(t, r)).  Lane exchange only; every lane takes part,
+// and the partner is always in the lane's own group of LN lanes.
 //   E = 8: m = k1 + 8 c + 64 d (lane c + 8 k1) -> register 7 - d of the lane
 //          (7 - c) + 8 (8 - k1) for k1 > 0, (8 - c) for k1 = 0 < c; lane 0
 //          keeps its own register (8 - d) mod 8.
-//   else:  m = r + E b (b = brev6(t)) -> register E - r of lane 63 - t, or,
-//          for r = 0, register 0 of lane brev6((64 - b) & 63).
-template <typename R, int E>
+//   else:  m = r + E b (b = brev(t)) -> register E - r of lane LN - 1 - t,
+//          or, for r = 0, register 0 of lane brev((LN - b) mod LN), passed
+//          as the wavefront lane `lane0`.
+template <typename R, int E, int LN = 64>
 __device__ __forceinline__ cx<R> mirror_val(const cx<R> (&v)[E], int r, int lane0) {
   const int t = threadIdx.x & 63;
   if constexpr (E == 8) {
+    static_assert(LN == 64, "the E = 8 transform spans the wavefront");
     const int c = t & 7, k1 = t >> 3;
     const int tp = k1 ? (7 - c) + 8 * (8 - k1) : ((8 - c) & 7);
     const cx<R> o = shfl_c(v[7 - r], tp);
@@ -286,7 +308,7 @@ __device__ __forceinline__ cx<R> mirror_val(const cx<R> (&v)[E], int r, int lane
     for (int q = 0; q < E; ++q) {
       // compile-time register selection: every lane takes the same register
       const int want = (r == 0) ? 0 : E - r;
-      if (q == want) out = shfl_c(v[q], r == 0 ? lane0 : 63 - t);
+      if (q == want) out = shfl_c(v[q], r == 0 ? lane0 : t ^ (LN - 1));
     }
     return out;
   }
@@ -301,21 +323,24 @@ __device__ __forceinline__ int sidx(int c, int e, int pitch) {
 
 // Phases B and C of a pass: the block's staged tile (LDS, after a barrier)
 // -> pencil registers, transform(s) (and the Green operator in the fused z
-// pass), -> output staging.  Returns the output rows per column; the caller
-// places the barrier before the output staging is read.
-template <typename R, int MODE, int XP, int E, typename WP, typename GZ>
+// pass), -> output staging.  `w` is the block's pencil held by this lane's
+// group of LN lanes and `t` the lane within that group.  Returns the output
+// rows per column; the caller places the barrier before the output staging
+// is read.
+template <typename R, int MODE, int XP, int E, int LN, typename WP, typename GZ>
 __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, bool packed, bool half, int cols,
                                            int w, int t, int mlane0, const Tile& tl, int j0, int pitch, R* sr,
-                                           cx<R>* sc, R* wscr, WP W, const LaneTw<R>& ltw, const GreenCol<R>* gcol,
+                                           cx<R>* sc, R* wscr, WP W, const LaneTw<R, LN>& ltw, const GreenCol<R>* gcol,
                                            GZ gz) {
-  constexpr int L = 64 * E;
+  constexpr int L = LN * E;
+  static_assert(LN == 64 || E != 8, "the E = 8 transform spans the wavefront");
   // ---------------- phase B: pencil -> registers, FFT ----------------
   cx<R> v[E];
   const int ca = packed ? 2 * w : w, cb = 2 * w + 1;   // columns of this pencil
   if (MODE == 0 || MODE == 2) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int x = t + 64 * j;
+      const int x = t + LN * j;
       int jn, sg;
       ext_src(kind, n, x, jn, sg);
       cx<R> z = mk<R>(0, 0);
@@ -328,11 +353,11 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
       v[j] = z;
     }
     if constexpr (E == 8) wave_fft8<R>(v, W, wscr, false);
-    else wave_fft<R, E>(v, gconst((const cx<R>*)d.tw), ltw, false);
+    else wave_fft<R, E, LN>(v, gconst((const cx<R>*)d.tw), ltw, false);
   } else {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int m = spec_pos<E>(t, j);   // inverse input layout: lane t, register j
+      const int m = spec_pos<E, LN>(t, j);   // inverse input layout: lane t, register j
       cx<R> z = mk<R>(0, 0);
       if (half) {
         // two Hermitian half spectra A (column ca) and B (column cb): Z = A + i B
@@ -352,7 +377,7 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
       v[j] = z;
     }
     if constexpr (E == 8) wave_fft8<R>(v, W, wscr, true);
-    else wave_fft<R, E>(v, gconst((const cx<R>*)d.tw), ltw, true);
+    else wave_fft<R, E, LN>(v, gconst((const cx<R>*)d.tw), ltw, true);
   }
 
   if (MODE == 2) {
@@ -364,8 +389,8 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
       cx<R> nv[E];
 #pragma unroll
       for (int k1 = 0; k1 < E; ++k1) {
-        const int m = spec_pos<E>(t, k1);
-        const cx<R> a = v[k1], b = conj(mirror_val<R, E>(v, k1, mlane0));
+        const int m = spec_pos<E, LN>(t, k1);
+        const cx<R> a = v[k1], b = conj(mirror_val<R, E, LN>(v, k1, mlane0));
         const cx<R> A = scl(add(a, b), (R)0.5);
         const cx<R> Bv = mk<R>((R)0.5 * (a.im - b.im), (R)-0.5 * (a.re - b.re));
         const int mk_ = m <= n / 2 ? m : n - m;
@@ -380,7 +405,7 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
     } else {
 #pragma unroll
       for (int k1 = 0; k1 < E; ++k1) {
-        const int m = spec_pos<E>(t, k1);
+        const int m = spec_pos<E, LN>(t, k1);
         int k;
         R fr, fi;
         if (!spec_src<R>(kind, n, m, k, fr, fi)) { v[k1] = mk<R>(0, 0); continue; }
@@ -397,7 +422,7 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
       }
     }
     if constexpr (E == 8) wave_fft8<R>(v, W, wscr, true);
-    else wave_fft<R, E>(v, gconst((const cx<R>*)d.tw), ltw, true);
+    else wave_fft<R, E, LN>(v, gconst((const cx<R>*)d.tw), ltw, true);
   }
 
   // ---------------- phase C: registers -> staging ----------------
@@ -409,7 +434,7 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
     const int opitch = XP ? M + 1 : cols + 1;
 #pragma unroll
     for (int k1 = 0; k1 < E; ++k1) {
-      const int m = spec_pos<E>(t, k1);
+      const int m = spec_pos<E, LN>(t, k1);
       // coefficient index carried by position m (inverse of the Table 1 map)
       int k = -1;
       R fr = 1, fi = 0;
@@ -421,7 +446,7 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
         default: if ((m & 1) && m < 2 * n) { k = (m - 1) >> 1; fr = 0; fi = (R)0.5; } break;
       }
       cx<R> pm = mk<R>(0, 0);
-      if (half) pm = conj(mirror_val<R, E>(v, k1, mlane0));    // shuffles: all lanes take part
+      if (half) pm = conj(mirror_val<R, E, LN>(v, k1, mlane0));    // shuffles: all lanes take part
       if (k < 0) continue;
       if (half) {
         const cx<R> a = v[k1];
@@ -439,7 +464,7 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
     const R invL = (R)1 / (R)L;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int x = t + 64 * j;
+      const int x = t + LN * j;
       // node j_node = x for x <= n; the periodic node n copies position 0
       if (x > n) continue;
       const int node = x;
@@ -459,8 +484,9 @@ __device__ __forceinline__ int wave_pencil(const PassDesc& d, int kind, int n, b
 
 // Phase D of the x passes: output staging -> memory.  Forward: the
 // coefficient rows; inverse: u^f += w - sum_k beta_k delta_k and the new
-// increment into the ring (FP64 accumulator).
-template <typename R, int MODE, int UD, int UX>
+// increment into the ring (FP64 accumulator).  RW: rows per wavefront (the
+// tile's rows / 8).
+template <typename R, int MODE, int UD, int UX, int RW = 2>
 __device__ __forceinline__ void wave_store_x(const PassDesc& d, const FM_GLOBAL Ctrl* C, const Tile& tl,
                                              int64_t out_blk, int outcnt, bool cout_, uint32_t eso, const R* sr,
                                              const cx<R>* sc, int w, int t) {
@@ -504,13 +530,12 @@ __device__ __forceinline__ void wave_store_x(const PassDesc& d, const FM_GLOBAL 
     FM_GLOBAL char* dw = (FM_GLOBAL char*)gmut((R*)d.ring) +
                          ((int64_t)C->slot_w * d.ring_stride + out_blk) * (int64_t)sizeof(R);
     FM_GLOBAL char* guf = (FM_GLOBAL char*)gmut(d.uf) + out_blk * (int64_t)sizeof(double);
-    // both rows of this wavefront: all loads first, then the stores
-    static_assert(2 * WAVE_PENCILS == 16, "two rows per wavefront");
+    // all rows of this wavefront: all loads first, then the stores
     for (int eb = t; eb < outcnt; eb += UX * 64) {
-      R dl[2][UX];
-      double uo[2][UX];
+      R dl[RW][UX];
+      double uo[RW][UX];
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
+      for (int r = 0; r < RW; ++r) {
         const int c = w + WAVE_PENCILS * r;
         const uint32_t rowe = (uint32_t)(c * s1);
 #pragma unroll
@@ -528,7 +553,7 @@ __device__ __forceinline__ void wave_store_x(const PassDesc& d, const FM_GLOBAL 
         }
       }
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
+      for (int r = 0; r < RW; ++r) {
         const int c = w + WAVE_PENCILS * r;
         const uint32_t rowe = (uint32_t)(c * s1);
 #pragma unroll
@@ -550,13 +575,19 @@ __device__ __forceinline__ void wave_store_x(const PassDesc& d, const FM_GLOBAL 
 // the axis length (n = L / S_f), the tile width, the element types and every
 // staging pitch; KIND = -1 reads them from the descriptor.  Global accesses
 // use 32-bit byte offsets from a per-block base: the plan keeps each
-// component's buffers below 4 GiB for these kernels.
-template <typename R, int MODE, int XP, int E, int KIND = -1, int PK = -1>
+// component's buffers below 4 GiB for these kernels.  LN < 64 gives every
+// group of LN lanes a pencil of its own (L = LN E; the block's tile is
+// 64 / LN times wider).
+template <typename R, int MODE, int XP, int E, int KIND = -1, int PK = -1, int LN = 64>
 __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restrict__ descs,
                                                        const int2* __restrict__ work,
                                                        const SolveDev* __restrict__ S) {
+  static_assert(LN == 64 || LN == 32 || LN == 16, "lanes per pencil");
+  constexpr int NPW = 64 / LN;                    // pencils per wavefront
+  constexpr int PPB = WAVE_PENCILS * NPW;         // pencils per block
+  constexpr int LPPB = 9 - lanes_log2(LN);        // log2 PPB
   extern __shared__ __align__(16) char smem[];
-  __shared__ GreenCol<R> gcol[2 * WAVE_PENCILS];
+  __shared__ GreenCol<R> gcol[2 * PPB];
   const int2 wk = work[blockIdx.x];
   const PassDesc& d = descs[wk.x];
   const FM_GLOBAL Ctrl* C = gconst(S[d.solve].ctrl);
@@ -567,7 +598,7 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   // solve's buffers stay allocated, and nothing is written for it.
   constexpr bool CTRL_FIRST = MODE == 0 && XP;
   if (CTRL_FIRST && C->status != ST_RUNNING) return;
-  constexpr int L = 64 * E;
+  constexpr int L = LN * E;
   constexpr bool SK = KIND >= 0;
   // rows loaded by the strided passes when the kind is fixed, and the
   // loads per thread that cover them in one batch
@@ -577,11 +608,11 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
                          : KIND == K_DCT1 ? NC + 1 : KIND == K_DST1 ? NC - 1 : NC;
   constexpr int CNT_OUT = !SK ? 0 : MODE != 0 ? NC + 1 : (PK == 1 && KIND == K_DFT) ? NC / 2 + 1
                           : KIND == K_DCT1 ? NC + 1 : KIND == K_DST1 ? NC - 1 : NC;
-  constexpr int STEP_C = WAVE_PENCILS * (PK == 1 ? 4 : 8);
+  constexpr int STEP_C = WAVE_THREADS / (PK == 1 ? 2 * PPB : PPB);
   const int kind = SK ? KIND : d.kind;
   const int n = SK ? L / kind_sf(KIND) : d.n;
   const bool packed = SK ? PK == 1 : d.packed != 0;
-  const int lcols = packed ? 4 : 3;             // tile width: 16 real or 8 complex columns
+  const int lcols = packed ? LPPB + 1 : LPPB;   // tile width: 2 PPB real or PPB complex columns
   const int cols = 1 << lcols;
   const bool half = packed && kind == K_DFT;
   // complex elements in and out (real DTT data travels packed as reals)
@@ -591,8 +622,9 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   const uint32_t esi = cin ? 2 * sizeof(R) : sizeof(R);
   const uint32_t eso = cout_ ? 2 * sizeof(R) : sizeof(R);
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
-  const int bt = brev6(t);                      // spectral lane order
-  const int mlane0 = brev6((64 - bt) & 63);     // lane of the partner of register 0
+  const int pen = w * NPW + t / LN, tp = t & (LN - 1);   // this lane's pencil, lane within it
+  const int bt = brev_ln<LN>(tp);               // spectral lane order
+  const int mlane0 = (t & ~(LN - 1)) + brev_ln<LN>((LN - bt) & (LN - 1));   // partner of register 0
   Tile tl;
   if (XP) { tl.p0b = wk.y * cols; tl.p1 = 0; }
   else { tl.p0b = (wk.y % d.tiles_p0) * cols; tl.p1 = wk.y / d.tiles_p0; }
@@ -601,8 +633,8 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   // first element of the block's tile, in elements of the input / output
   const int64_t in_blk = XP ? (int64_t)tl.p0b * d.in_s1 : (int64_t)tl.p1 * d.in_s1 + tl.p0b;
   const int64_t out_blk = XP ? (int64_t)tl.p0b * d.out_s1 : (int64_t)tl.p1 * d.out_s1 + tl.p0b;
-  LaneTw<R> ltw;
-  if constexpr (E != 8) ltw = lane_twiddles<R>(W, L);
+  LaneTw<R, LN> ltw;
+  if constexpr (E != 8) ltw = lane_twiddles<R, LN>(W, L);
   // E = 8: per-wave transpose scratch first, then the staging tile
   R* wscr = (R*)smem + (E == 8 ? w * WT_SIZE : 0);
   char* stage = smem + (E == 8 ? WAVE_PENCILS * WT_SIZE * sizeof(R) : 0);
@@ -730,14 +762,15 @@ __global__ void __launch_bounds__(WAVE_THREADS) k_wave(const PassDesc* __restric
   const FM_GLOBAL char* zs2 = (const FM_GLOBAL char*)gconst(d.gs2[2]);
   const FM_GLOBAL char* zc2 = (const FM_GLOBAL char*)gconst(d.gc2[2]);
   auto gz = [&](int k) { return mk<R>((R)gld<double>(zs2, 8u * k), (R)gld<double>(zc2, 8u * k)); };
-  const int outcnt = wave_pencil<R, MODE, XP, E>(d, kind, n, packed, half, cols, w, t, mlane0, tl, j0, pitch, sr, sc,
-                                                wscr, TwGlobal<R>{W}, ltw, gcol, gz);
+  const int outcnt = wave_pencil<R, MODE, XP, E, LN>(d, kind, n, packed, half, cols, pen, tp, mlane0, tl, j0, pitch,
+                                                    sr, sc, wscr, TwGlobal<R>{W}, ltw, gcol, gz);
   __syncthreads();
 
   // ---------------- phase D: staging -> memory (coalesced) ----------------
   constexpr int UD = SK && !XP ? (CNT_OUT + STEP_C - 1) / STEP_C : 8;
   if (XP) {
-    wave_store_x<R, MODE, UD, SK ? (CNT_OUT + 63) / 64 : 4>(d, C, tl, out_blk, outcnt, cout_, eso, sr, sc, w, t);
+    wave_store_x<R, MODE, UD, SK ? (CNT_OUT + 63) / 64 : 4 / NPW, 2 * NPW>(d, C, tl, out_blk, outcnt, cout_, eso,
+                                                                           sr, sc, w, t);
   } else {
     FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) + out_blk * (int64_t)eso;
     const int opitch = cols + 1;
@@ -885,7 +918,7 @@ __global__ void __launch_bounds__(WAVE_THREADS, (MODE == 2 || KIND == K_DFT) ? 1
     if (item + (int)gridDim.x < nwork) issue(item + gridDim.x);
     if (run) {
       auto gz = [&](int k) { return gtab[k]; };
-      const int outcnt = wave_pencil<R, MODE, 0, E>(d, KIND, n, packed, half, cols, w, t, mlane0, tl, j0, pitch,
+      const int outcnt = wave_pencil<R, MODE, 0, E, 64>(d, KIND, n, packed, half, cols, w, t, mlane0, tl, j0, pitch,
                                                     sr, sc, wscr, TwLds<R>{tw}, ltw, gcol, gz);
       __syncthreads();
       FM_GLOBAL char* gout = (FM_GLOBAL char*)gmut((char*)d.out) +
@@ -1045,7 +1078,7 @@ __global__ void __launch_bounds__(WAVE_THREADS, (KIND == K_DFT || MODE == 1) ? 1
     const bool run = C->status == ST_RUNNING;
     if (item + (int)gridDim.x < nwork) issue(item + gridDim.x);
     if (run) {
-      const int outcnt = wave_pencil<R, MODE, 1, E>(d, KIND, n, packed, half, cols, w, t, mlane0, tl, j0, pitch,
+      const int outcnt = wave_pencil<R, MODE, 1, E, 64>(d, KIND, n, packed, half, cols, w, t, mlane0, tl, j0, pitch,
                                                     sr, sc, wscr, TwLds<R>{tw}, ltw, nogreen, nogz);
       __syncthreads();
       wave_store_x<R, MODE, 8, (n + 1 + 63) / 64>(d, C, tl, (int64_t)tl.p0b * d.out_s1, outcnt, cout_, eso, sr, sc, w, t);

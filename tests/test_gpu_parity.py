@@ -60,8 +60,12 @@ def test_green_apply(B, prec, seed, n, scheme, green):
 # Grids whose pencil lengths L = 64 E reach every wavefront-kernel variant
 # (E = 1, 2, 3, 4, 5, 6, 8, 12) on the x, y and z axes, for each transform kind;
 # the 512-point DFT shapes reach the E = 8 periodic (r2c and complex) kernels.
+# The 16-, 32-, 48- and 96-point pencils (n = 8, 16, 24, 48; DFT and the
+# doubled DTT lengths) take the kernels with two or four pencils per
+# wavefront (32 / 16 lanes each), also on the x passes with their wider tiles.
 WAVE_SHAPES = [(256, 6, 5), (6, 256, 5), (5, 6, 256), (96, 160, 6), (192, 7, 128), (64, 32, 384),
-               (512, 5, 6), (6, 512, 5), (5, 6, 512)]
+               (512, 5, 6), (6, 512, 5), (5, 6, 512),
+               (48, 16, 5), (16, 48, 7), (5, 24, 48), (24, 7, 16), (8, 48, 24)]
 BC_PATTERNS = {
     "P": [W.P, W.P], "N": [W.N, W.N], "D": [W.D, W.D], "ND": [W.N, W.D], "DN": [W.D, W.N],
 }
