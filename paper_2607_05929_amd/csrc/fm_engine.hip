@@ -552,16 +552,24 @@ struct fm_plan {
 // A set of solves advanced together.
 // Pass kernel variants: generic (0), wavefront E = 1,2,3,4,5,6,12,16 (1-9,
 // 7 unused), for E = 8 one bucket per transform kind and packing
-// (10 + 2 kind + packed), whose kernels fix both at compile time, and the
-// 32- and 16-lane pencils with E = 1 and 3 (20-23).
-constexpr int NBUCKET = 24;
+// (10 + 2 kind + packed), whose kernels fix both at compile time, the
+// 32- and 16-lane pencils with E = 1 and 3 (20-23), and per kind and packing
+// (+ 2 kind + packed) the E = 3 pencils on 64 lanes (24) and on 32 lanes
+// (34), and the E = 1 (44) and E = 2 (54) pencils on 64 lanes; buckets 1-3
+// and 21 stay empty.
+constexpr int NBUCKET = 64;
 inline int bucket_of(int E, int LN, int kind, int packed) {
+  const int pk = 2 * kind + (packed ? 1 : 0);
+  if (E == 3 && LN >= 32) return (LN == 64 ? 24 : 34) + pk;
+  if ((E == 1 || E == 2) && LN == 64) return (E == 1 ? 44 : 54) + pk;
   if (E && LN != 64) return 20 + (LN == 16 ? 2 : 0) + (E == 3 ? 1 : 0);
   switch (E) { case 1: return 1; case 2: return 2; case 3: return 3; case 4: return 4; case 5: return 5;
                case 6: return 6; case 8: return 10 + 2 * kind + (packed ? 1 : 0); case 12: return 8;
                case 16: return 9; default: return 0; }
 }
-constexpr int E_of_bucket[NBUCKET] = {0, 1, 2, 3, 4, 5, 6, 8, 12, 16, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 1, 3, 1, 3};
+constexpr int E_of_bucket[NBUCKET] = {0, 1, 2, 3, 4, 5, 6, 8, 12, 16, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 1, 3, 1, 3,
+                                      3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3,
+                                      1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
 
 struct Group {
   int prec = 0;
@@ -1164,13 +1172,59 @@ void launch_w8_kind(int kind, int packed, dim3 grid, size_t lds, hipStream_t st,
   }
 }
 
+// The pencils of grids of 32-96 cells (L = 64, 128 and 192 on 64 lanes, L =
+// 96 on 32): in FP32 compiled per transform kind and packing like the E = 8
+// kernels (n, element types and pitches fixed at compile time), in FP64 the
+// descriptor-driven kernel.  Returns false for a combination that has no
+// kernel (x passes are always packed).
+template <int MODE, int XP, int E, int LN, int KIND>
+bool launch_wks(int packed, dim3 grid, size_t lds, hipStream_t st, const PassDesc* P, const int2* wl,
+                const SolveDev* S) {
+  if (packed) {
+    hipLaunchKernelGGL((k_wave<float, MODE, XP, E, KIND, 1, LN>), grid, dim3(WAVE_THREADS), lds, st, P, wl, S);
+    return true;
+  }
+  if constexpr (!XP) {
+    hipLaunchKernelGGL((k_wave<float, MODE, XP, E, KIND, 0, LN>), grid, dim3(WAVE_THREADS), lds, st, P, wl, S);
+    return true;
+  }
+  return false;
+}
+
+template <typename R, int MODE, int XP, int E, int LN>
+bool launch_wk(int kind, int packed, dim3 grid, size_t lds, hipStream_t st, const PassDesc* P, const int2* wl,
+               const SolveDev* S) {
+  if constexpr (sizeof(R) == 4) {
+    switch (kind) {
+      case K_DFT: return launch_wks<MODE, XP, E, LN, K_DFT>(packed, grid, lds, st, P, wl, S);
+      case K_DCT1: return launch_wks<MODE, XP, E, LN, K_DCT1>(packed, grid, lds, st, P, wl, S);
+      case K_DST1: return launch_wks<MODE, XP, E, LN, K_DST1>(packed, grid, lds, st, P, wl, S);
+      case K_DCT3: return launch_wks<MODE, XP, E, LN, K_DCT3>(packed, grid, lds, st, P, wl, S);
+      default: return launch_wks<MODE, XP, E, LN, K_DST3>(packed, grid, lds, st, P, wl, S);
+    }
+  } else {
+    hipLaunchKernelGGL((k_wave<R, MODE, XP, E, -1, -1, LN>), grid, dim3(WAVE_THREADS), lds, st, P, wl, S);
+    return true;
+  }
+}
+
 template <typename R, int MODE, int XP>
 int launch_bucket(const Group& G, int pk, int b) {
   const int2* wl = G.wl[WL_PASS0 + pk] + G.boff[pk][b];
   const dim3 grid((unsigned)G.bn[pk][b]);
   const size_t lds = G.blds[pk][b];
   hipStream_t st = G.stream;
-  if (b >= 20) {
+  if (b >= 24) {
+    const int set = (b - 24) / 10, kind = ((b - 24) % 10) >> 1, packed = b & 1;
+    bool ok;
+    switch (set) {
+      case 0: ok = launch_wk<R, MODE, XP, 3, 64>(kind, packed, grid, lds, st, G.P, wl, G.S); break;
+      case 1: ok = launch_wk<R, MODE, XP, 3, 32>(kind, packed, grid, lds, st, G.P, wl, G.S); break;
+      case 2: ok = launch_wk<R, MODE, XP, 1, 64>(kind, packed, grid, lds, st, G.P, wl, G.S); break;
+      default: ok = launch_wk<R, MODE, XP, 2, 64>(kind, packed, grid, lds, st, G.P, wl, G.S); break;
+    }
+    if (!ok) return fail(FM_E_INVALID_ARG, "internal: no wavefront kernel for an unpacked x pass");
+  } else if (b >= 20) {
     switch (b) {
       case 20: hipLaunchKernelGGL((k_wave<R, MODE, XP, 1, -1, -1, 32>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
       case 21: hipLaunchKernelGGL((k_wave<R, MODE, XP, 3, -1, -1, 32>), grid, dim3(WAVE_THREADS), lds, st, G.P, wl, G.S); break;
