@@ -275,13 +275,17 @@ int fm_set_graph_launch(int enable);
  * stored choice without timing (ms then holds -1 everywhere).  Otherwise, for each of the five axis passes
  * (x forward, y forward, z forward+Green+inverse, y inverse, x inverse),
  * times n_iter iterations of *step with every applicable candidate kernel --
- * 0 the wavefront kernel (pencil lengths 64E), 1..3 the generic LDS kernel
- * with the largest, half and quarter number of transforms per block -- and
- * keeps the fastest per pass for this plan's later solves and batches.
+ * 0 the wavefront kernel (pencil lengths 64E, or 32E / 16E for E in {1, 3}),
+ * 1..3 the generic LDS kernel with the largest, half and quarter number of
+ * transforms per block -- and keeps the fastest per pass for this plan's
+ * later solves and batches.  A pass whose launch would hold fewer than
+ * about four blocks per compute unit is timed with its tiles repeated up to
+ * that fill (time divided by the repetitions): its cost when other solves
+ * share the device, as in fm_batch_solve and the server.
  * choice[5] (host, optional) receives the chosen candidate per pass;
  * ms[4*5] (host, optional) the mean time in ms per candidate and pass (-1 if
- * not applicable).  Overwrites the plan's displacement (reset it with
- * fm_set_material before solving). */
+ * not applicable).  Overwrites the plan's displacement and spectral buffers
+ * (reset it with fm_set_material before solving). */
 int fm_autotune(fm_plan* plan, const fm_load_step* step, int32_t n_iter, int32_t* choice, double* ms);
 
 /* Iterations performed by the last fm_solve / fm_batch_solve of this plan. */

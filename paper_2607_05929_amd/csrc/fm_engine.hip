@@ -1908,7 +1908,55 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
   return FM_OK;
 }
 
-int fm_profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, double* ms) {
+}  // extern "C"
+
+namespace {
+
+// A pass slot's work list repeated `reps` times (bucket by bucket), so that
+// one launch holds about four blocks per compute unit.
+struct FillList {
+  int2* d = nullptr;
+  int reps = 1;
+  int64_t boff[NBUCKET]{}, bn[NBUCKET]{};
+};
+
+int make_fill_list(const Group& G, int slot, FillList& f) {
+  const int64_t n = G.nwl[WL_PASS0 + slot];
+  const int64_t target = 4LL * (g_num_cu > 0 ? g_num_cu : 256);
+  f.reps = (n == 0 || n >= target) ? 1 : (int)cdiv(target, n);
+  if (f.reps == 1) return 0;
+  std::vector<int2> h((size_t)n), r;
+  HIPCHK(hipMemcpyAsync(h.data(), G.wl[WL_PASS0 + slot], sizeof(int2) * n, hipMemcpyDeviceToHost, G.stream));
+  HIPCHK(hipStreamSynchronize(G.stream));
+  r.reserve((size_t)n * f.reps);
+  for (int b = 0; b < NBUCKET; ++b) {
+    f.boff[b] = (int64_t)r.size();
+    f.bn[b] = G.bn[slot][b] * f.reps;
+    for (int k = 0; k < f.reps; ++k)
+      r.insert(r.end(), h.begin() + G.boff[slot][b], h.begin() + G.boff[slot][b] + G.bn[slot][b]);
+  }
+  HIPCHK(hipMalloc(&f.d, sizeof(int2) * r.size()));
+  HIPCHK(hipMemcpyAsync(f.d, r.data(), sizeof(int2) * r.size(), hipMemcpyHostToDevice, G.stream));
+  return 0;
+}
+
+// Exchange a slot's work list with its repeated form (called again to undo).
+void swap_fill_list(Group& G, int slot, FillList& f) {
+  std::swap(G.wl[WL_PASS0 + slot], f.d);
+  for (int b = 0; b < NBUCKET; ++b) {
+    std::swap(G.boff[slot][b], f.boff[b]);
+    std::swap(G.bn[slot][b], f.bn[b]);
+  }
+}
+
+// Per-kernel mean times of n_iter iterations of *step.  With `fill`, each
+// transform pass whose launch would leave the device partly idle runs with
+// its tiles repeated until it holds about four blocks per compute unit, and
+// its time is divided by the repetitions: the pass's cost when other solves
+// fill the device, as in a batch or the server.  The repeated tiles write
+// the same outputs (the z pass in place), so the plan's fields hold no
+// solution afterwards.
+int profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, double* ms, bool fill) {
   if (!p || !step || n_iter < 1 || !ms) return fail(FM_E_INVALID_ARG, "null argument");
   if (!p->material_set) return fail(FM_E_STATE, "fm_set_material must be called first");
   if (int rc = check_tractions(p->d, step, 1)) return rc;
@@ -1921,42 +1969,63 @@ int fm_profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, 
   c.tol = -1.0;                 // never converged
   c.max_iter = 1 << 30;
   HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, p->stream));
-  hipEvent_t ev[FM_N_KERNELS + 1];
-  for (int i = 0; i <= FM_N_KERNELS; ++i) HIPCHK(hipEventCreate(&ev[i]));
   for (int k = 0; k < FM_N_KERNELS; ++k) ms[k] = 0;
-  const Group& G = *p->self;
+  Group& G = *p->self;
   hipStream_t st = p->stream;
+  // kernels 4..8 are the pass slots 0..4 (slot 2: the fused z pass)
+  FillList fl[5];
+  std::vector<hipEvent_t> evs((size_t)n_iter * (FM_N_KERNELS + 1), nullptr);
+  auto release = [&]() {
+    (void)hipStreamSynchronize(st);
+    for (auto& f : fl)
+      if (f.d) { (void)hipFree(f.d); f.d = nullptr; }
+    for (auto& x : evs)
+      if (x) { (void)hipEventDestroy(x); x = nullptr; }
+  };
+  for (int sl = 0; fill && sl < 5 && !rc; ++sl) rc = make_fill_list(G, sl, fl[sl]);
+  for (size_t i = 0; i < evs.size() && !rc; ++i)
+    if (hipEventCreate(&evs[i]) != hipSuccess) rc = fail(FM_E_HIP, "event create");
+  if (rc) { release(); return rc; }
   // all iterations are enqueued before the first wait, so the stream runs the
   // kernels back to back and each interval is one kernel's execution
-  std::vector<hipEvent_t> evs((size_t)n_iter * (FM_N_KERNELS + 1));
-  for (auto& x : evs) HIPCHK(hipEventCreate(&x));
-  for (int it = 0; it < n_iter; ++it) {
+  for (int it = 0; it < n_iter && !rc; ++it) {
     hipEvent_t* e = &evs[(size_t)it * (FM_N_KERNELS + 1)];
-    HIPCHK(hipEventRecord(e[0], st));
-    for (int k = 0; k < FM_N_KERNELS; ++k) {
+    if (hipEventRecord(e[0], st) != hipSuccess) rc = fail(FM_E_HIP, "event record");
+    for (int k = 0; k < FM_N_KERNELS && !rc; ++k) {
+      FillList* f = (k >= 4 && k <= 8 && fl[k - 4].reps > 1) ? &fl[k - 4] : nullptr;
+      if (f) swap_fill_list(G, k - 4, *f);
       if (p->d.prec == FM_FP64) rc = launch_one<double>(G, k);
       else rc = launch_one<float>(G, k);
-      if (rc) return rc;
-      HIPCHK(hipEventRecord(e[k + 1], st));
+      if (f) swap_fill_list(G, k - 4, *f);
+      if (!rc && hipEventRecord(e[k + 1], st) != hipSuccess) rc = fail(FM_E_HIP, "event record");
     }
   }
-  HIPCHK(hipEventSynchronize(evs.back()));
-  for (int it = 0; it < n_iter; ++it) {
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(FM_E_HIP, "profile synchronize");
+  for (int it = 0; it < n_iter && !rc; ++it) {
     hipEvent_t* e = &evs[(size_t)it * (FM_N_KERNELS + 1)];
     for (int k = 0; k < FM_N_KERNELS; ++k) {
       float tms = 0;
-      HIPCHK(hipEventElapsedTime(&tms, e[k], e[k + 1]));
-      ms[k] += tms / n_iter;
+      if (hipEventElapsedTime(&tms, e[k], e[k + 1]) != hipSuccess) { rc = fail(FM_E_HIP, "event time"); break; }
+      const int reps = (k >= 4 && k <= 8) ? fl[k - 4].reps : 1;
+      ms[k] += tms / n_iter / reps;
     }
   }
-  for (auto& x : evs) HIPCHK(hipEventDestroy(x));
-  for (int i = 0; i <= FM_N_KERNELS; ++i) HIPCHK(hipEventDestroy(ev[i]));
+  release();
+  if (rc) return rc;
   c.status = ST_IDLE;
   HIPCHK(hipMemcpyAsync(dev_ctrl(p), &c, sizeof(Ctrl), hipMemcpyHostToDevice, st));
   rc = unfold_ustar(p);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(st));
   return FM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fm_profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, double* ms) {
+  return profile_iterations(p, step, n_iter, ms, false);
 }
 
 }  // extern "C"
@@ -2016,7 +2085,7 @@ int fm_autotune(fm_plan* p, const fm_load_step* step, int32_t n_iter, int32_t* c
     p->g = g2;
     int rc = rebuild_plan_group(p);
     if (rc) { p->g = saved; rebuild_plan_group(p); return rc; }
-    rc = fm_profile_iterations(p, step, n_iter, tms);
+    rc = profile_iterations(p, step, n_iter, tms, true);
     if (rc) { p->g = saved; rebuild_plan_group(p); return rc; }
     for (int pass = 0; pass < 5; ++pass) {
       if (!valid[pass]) continue;
