@@ -232,9 +232,10 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
   }
   for (int it = 0; it < 80 && nr >= LawTol<R>::cp; ++it) {
     // Newton matrix [[A, b], [c^T, d6]] on (sigma_M, dGamma): A = compliance +
-    // sum_s dt a_s P_s P_s^T is symmetric positive definite, so the step is a
-    // Cholesky solve of A against the residual and b, closed by the scalar
-    // Schur complement (no pivoting; the lower triangle of A only)
+    // sum_s dt a_s P_s P_s^T is symmetric positive definite, so the step is an
+    // L D L^T solve of A against the residual and b, closed by the scalar
+    // Schur complement (no pivoting; the lower triangle of A only; six
+    // reciprocals of the pivots and no square root or further division)
     const R hG = th0 * exp(-th0 * (Gn + dG) * ihs);
     const R itc = (R)1 / tc;
     R A[6][6], bv[6], cv[6];
@@ -266,41 +267,50 @@ __device__ void cp_update(PT P, const R em[6], const R epn[6], R Gn, R dt, R sm[
       }
       d6 += dt * nx * fabs(gs) * itc * hG;
     }
+    // A = L D L^T: unit lower L in the strict lower triangle of A, D in dd,
+    // 1 / D in id
     bool spd = true;
+    R dd[6], id[6];
 #pragma unroll
     for (int j2 = 0; j2 < 6; ++j2) {
+      R v[6];
       R dj = A[j2][j2];
 #pragma unroll
-      for (int k = 0; k < j2; ++k) dj -= A[j2][k] * A[j2][k];
+      for (int k = 0; k < j2; ++k) {
+        v[k] = A[j2][k] * dd[k];
+        dj -= A[j2][k] * v[k];
+      }
       spd = spd && dj > 0;
-      const R ljj = sqrt(fmax(dj, (R)1e-300)), il = (R)1 / ljj;
-      A[j2][j2] = ljj;
+      dd[j2] = dj;
+      id[j2] = (R)1 / fmax(dj, (R)1e-300);
 #pragma unroll
       for (int i = j2 + 1; i < 6; ++i) {
         R t = A[i][j2];
 #pragma unroll
-        for (int k = 0; k < j2; ++k) t -= A[i][k] * A[j2][k];
-        A[i][j2] = t * il;
+        for (int k = 0; k < j2; ++k) t -= A[i][k] * v[k];
+        A[i][j2] = t * id[j2];
       }
     }
     if (!spd) break;
-    // z1 = A^-1 Rs, z2 = A^-1 b (forward then backward substitution)
+    // z1 = A^-1 Rs, z2 = A^-1 b (forward substitution, pivots, backward)
     R z1[6], z2[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       R t1 = Rs[i], t2 = bv[i];
 #pragma unroll
       for (int k = 0; k < i; ++k) { t1 -= A[i][k] * z1[k]; t2 -= A[i][k] * z2[k]; }
-      z1[i] = t1 / A[i][i];
-      z2[i] = t2 / A[i][i];
+      z1[i] = t1;
+      z2[i] = t2;
     }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) { z1[i] *= id[i]; z2[i] *= id[i]; }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
       R t1 = z1[i], t2 = z2[i];
 #pragma unroll
       for (int k = i + 1; k < 6; ++k) { t1 -= A[k][i] * z1[k]; t2 -= A[k][i] * z2[k]; }
-      z1[i] = t1 / A[i][i];
-      z2[i] = t2 / A[i][i];
+      z1[i] = t1;
+      z2[i] = t2;
     }
     R cz1 = 0, cz2 = 0;
 #pragma unroll
