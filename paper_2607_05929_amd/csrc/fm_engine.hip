@@ -259,7 +259,7 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
   g.sd_nt[2] = (int)cdiv(g.N[2], g.sd_zc);
   g.ntile_s = (int)(sd_per_slab * g.sd_nt[2]);
   g.ntile_v = (int)cdiv(g.Nv, SPACE_TILE);
-  g.ntile_d = (int)cdiv(g.Nn, SPACE_TILE);
+  g.ntile_d = (int)cdiv(g.Nn, GRAM_TILE);
   g.ntile_c0 = 0;
   if (g.c0) {
     // shared frequencies per axis: the cosine transform's set for a

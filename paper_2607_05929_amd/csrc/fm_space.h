@@ -26,6 +26,7 @@ constexpr int STALL_ITERS = 200;   // iterations without a 1 % better error (sta
 constexpr int RS64_STALL = 8;      // same, for an FP32 plan to move its real-space step to FP64
 constexpr int RS64_WIN = 12;       // window of the convergence-rate test of that move
 constexpr int SPACE_TILE = 1024;   // voxels / nodes per 256-thread block (4 per thread)
+constexpr int GRAM_TILE = 4096;    // nodes per 256-thread Gram block (16 per thread)
 
 __device__ __forceinline__ int vidx(int l, int q) {
   // Voigt index of the symmetric pair (l, q): xx yy zz yz xz xy
@@ -921,8 +922,10 @@ __global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : (sizeof(R) == 4 && 
 
 // Gram matrix of the residual window, on Anderson steps only.  Dismissed
 // nodes hold D = 0, so every node enters without a mask.  Each thread takes
-// SPACE_TILE / 256 nodes and issues all of a component's loads before using
-// them; products are summed per thread in R, the block in FP64.
+// GRAM_TILE / 256 nodes in chunks of four, issuing all of a component's
+// loads in a chunk before using them; products are summed per chunk in R,
+// across chunks and the block in FP64.  The large tile keeps the
+// block partials few: one block per solve reduces them (k_alpha).
 template <typename R>
 __global__ void __launch_bounds__(256) k_gram(const SolveDev* __restrict__ S, const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
@@ -930,36 +933,42 @@ __global__ void __launch_bounds__(256) k_gram(const SolveDev* __restrict__ S, co
   const FM_GLOBAL Ctrl* C = gconst(s.ctrl);
   if (C->status != ST_RUNNING || !C->aa_pending) return;
   const int k = C->win_n;
-  constexpr int SUB = SPACE_TILE / 256;
+  constexpr int SUB = 4, CHUNKS = GRAM_TILE / (256 * SUB);
   const FM_GLOBAL R* slot[MAX_DEPTH];
 #pragma unroll
   for (int a = 0; a < MAX_DEPTH; ++a)
     slot[a] = gconst((const R*)s.Dring) + (int64_t)(a < k ? C->win_slot[a] : 0) * 3 * s.Nn;
-  R acc[NGRAM];
-#pragma unroll
-  for (int i = 0; i < NGRAM; ++i) acc[i] = 0;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    R d[SUB][MAX_DEPTH];
-#pragma unroll
-    for (int sub = 0; sub < SUB; ++sub) {
-      const int64_t v = (int64_t)w.y * SPACE_TILE + sub * 256 + threadIdx.x;
-#pragma unroll
-      for (int a = 0; a < MAX_DEPTH; ++a) d[sub][a] = (a < k && v < s.Nn) ? slot[a][q * s.Nn + v] : (R)0;
-    }
-#pragma unroll
-    for (int sub = 0; sub < SUB; ++sub) {
-      int t = 0;
-#pragma unroll
-      for (int a = 0; a < MAX_DEPTH; ++a)
-#pragma unroll
-        for (int b = a; b < MAX_DEPTH; ++b) acc[t++] += d[sub][a] * d[sub][b];
-    }
-  }
-  __shared__ double outp[NGRAM];
   double accd[NGRAM];
 #pragma unroll
-  for (int i = 0; i < NGRAM; ++i) accd[i] = (double)acc[i];
+  for (int i = 0; i < NGRAM; ++i) accd[i] = 0;
+  for (int ch = 0; ch < CHUNKS; ++ch) {
+    const int64_t v0 = (int64_t)w.y * GRAM_TILE + ch * (256 * SUB) + threadIdx.x;
+    if (v0 >= s.Nn) break;
+    R acc[NGRAM];
+#pragma unroll
+    for (int i = 0; i < NGRAM; ++i) acc[i] = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      R d[SUB][MAX_DEPTH];
+#pragma unroll
+      for (int sub = 0; sub < SUB; ++sub) {
+        const int64_t v = v0 + sub * 256;
+#pragma unroll
+        for (int a = 0; a < MAX_DEPTH; ++a) d[sub][a] = (a < k && v < s.Nn) ? slot[a][q * s.Nn + v] : (R)0;
+      }
+#pragma unroll
+      for (int sub = 0; sub < SUB; ++sub) {
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < MAX_DEPTH; ++a)
+#pragma unroll
+          for (int b = a; b < MAX_DEPTH; ++b) acc[t++] += d[sub][a] * d[sub][b];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NGRAM; ++i) accd[i] += (double)acc[i];
+  }
+  __shared__ double outp[NGRAM];
   block_sum<NGRAM>(accd, outp);
   __syncthreads();
   if (threadIdx.x < NGRAM) gmut(s.part_g)[(int64_t)w.y * NGRAM + threadIdx.x] = outp[threadIdx.x];

@@ -5,12 +5,12 @@
 // that the 32-, 48- and 96-point pencils of small grids also take the
 // register transform instead of the generic LDS kernel.
 //
-// A block of 8 wavefronts owns a tile of 8 (64 / LN) pencils (16 real columns
-// packed two per pencil, or 8 complex columns, per 64 lanes per pencil):
-// small blocks so that several fit a
-// compute unit and one block's loads overlap another's arithmetic.  The tile
-// is loaded with coalesced 64-byte row segments (whole rows along x) into an
-// LDS staging array; each wavefront then gathers its pencil's virtual
+// A block of 8 wavefronts owns a tile of 8 * 64 / LN pencils (two real
+// columns packed per pencil, or one complex column: 16 or 8 columns at
+// LN = 64): small blocks so that several fit a compute unit and one block's
+// loads overlap another's arithmetic.  The tile is loaded with coalesced row
+// segments (64 bytes at LN = 64; whole rows along x) into an LDS staging
+// array; each group of LN lanes then gathers its pencil's virtual
 // extension (Table 1) straight into registers, lane t holding positions
 // t + LN j (j < E), and transforms it with
 //   X[k1 + E k2] = sum_t W_L^{t k1} W_LN^{t k2} sum_j x[t + LN j] W_E^{j k1}:
@@ -27,7 +27,7 @@
 
 namespace fm {
 
-constexpr int WAVE_PENCILS = 8;         // wavefronts (pencils) per block
+constexpr int WAVE_PENCILS = 8;         // wavefronts per block (its pencils at 64 lanes per pencil)
 constexpr int WAVE_THREADS = 64 * WAVE_PENCILS;
 
 __host__ __device__ inline bool wave_E_ok(int E) {
