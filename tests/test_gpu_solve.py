@@ -165,6 +165,36 @@ def test_batch_equals_alone(B):
         assert e < 1e-5
 
 
+def test_autotuned_batch_matches_untuned(B):
+    """Plans autotuned one at a time (small plans' passes timed with their
+    tiles repeated to fill the device) run together as one batch: every
+    member converges to the untuned batch's result, and a 24^3 member (48-
+    and 24-point pencils: 16-lane wavefront kernels, generic DFT) matches the
+    oracle."""
+    rng = np.random.default_rng(9)
+    probs = _batch_problems() + [W.random_rve(rng, n, prec=W.FP32_MIXED, tol=1e-6) for n in (24, 48)]
+    plans = [B.Plan(p, W.FP32_MIXED) for p in probs]
+    try:
+        for pl in plans:
+            info = pl.autotune(n_iter=2)
+            assert all(c >= 0 for c in info["choice"])
+        res = B.batch_solve(probs, plans=plans)
+    finally:
+        for pl in plans:
+            pl.close()
+    ref = B.batch_solve(probs, prec=W.FP32_MIXED)
+    for p, r, q in zip(probs, res, ref):
+        e = rel_err(r["macro_sigma"], q["macro_sigma"])
+        print(f"tuned batch member n={p.n} iters {r['iters']} untuned {q['iters']} macro diff {e:.2e}", flush=True)
+        assert r["rc"] == 0 and q["rc"] == 0
+        assert e < 1e-5
+    k = len(_batch_problems())
+    oref = osolver.solve(probs[k])
+    e = rel_err(res[k]["macro_sigma"], oref["macro_sigma"])
+    print(f"tuned 24^3 member macro err vs oracle {e:.2e}", flush=True)
+    assert e < 1e-5
+
+
 def test_batch_long_pencils_equals_alone(B):
     """A batch whose solves put 512-point pencils on different axes: the
     persistent pipelined pass kernels take work items of several solves in
