@@ -274,9 +274,13 @@ int make_geometry(const fm_plan_desc* d, Geometry& g) {
 }
 
 // Layout of a plan workspace: offsets of every buffer.
+// Blocks of one autotuning launch of a small plan's pass (its tile list
+// repeated up to this count: about four per compute unit of the 256).
+constexpr int FILL_BLOCKS = 1024;
+
 struct Layout {
   size_t ctrl, log, uf, Dring, dring, specA, specB, specC, c0tab, mat, mlaw, mtab, state, sig, part_s, part_d,
-      part_g, tw, gtab, group, total;
+      part_g, fill, tw, gtab, group, total;
   size_t tw_off[3][3];
   size_t g_off[3][3];   // green tables per comp, axis: s2 (M doubles), c2 (M doubles)
   size_t group_bytes;
@@ -370,6 +374,7 @@ void make_layout(const fm_plan_desc* d, const Geometry& g, Layout& L) {
   L.part_s = take(8 * NPART_S * (size_t)g.ntile_s);
   L.part_d = take(8 * (size_t)g.ntile_d);
   L.part_g = take(8 * NGRAM * (size_t)g.ntile_d);
+  L.fill = take(sizeof(int2) * 5 * 2 * FILL_BLOCKS);   // repeated tile lists of the five passes (autotuner)
   for (int q = 0; q < 3; ++q)
     for (int a = 0; a < 3; ++a) L.tw_off[q][a] = take(2 * R * (size_t)g.L[q][a]);
   for (int q = 0; q < 3; ++q)
@@ -1913,17 +1918,17 @@ int fm_residual(fm_plan* p, const fm_load_step* step, const double* d_uf, double
 namespace {
 
 // A pass slot's work list repeated `reps` times (bucket by bucket), so that
-// one launch holds about four blocks per compute unit.
+// one launch holds about FILL_BLOCKS blocks; kept in the plan workspace's
+// region for it (fewer than 2 FILL_BLOCKS entries per slot).
 struct FillList {
   int2* d = nullptr;
   int reps = 1;
   int64_t boff[NBUCKET]{}, bn[NBUCKET]{};
 };
 
-int make_fill_list(const Group& G, int slot, FillList& f) {
+int make_fill_list(const Group& G, int slot, int2* region, FillList& f) {
   const int64_t n = G.nwl[WL_PASS0 + slot];
-  const int64_t target = 4LL * (g_num_cu > 0 ? g_num_cu : 256);
-  f.reps = (n == 0 || n >= target) ? 1 : (int)cdiv(target, n);
+  f.reps = (n == 0 || n >= FILL_BLOCKS) ? 1 : (int)cdiv(FILL_BLOCKS, n);
   if (f.reps == 1) return 0;
   std::vector<int2> h((size_t)n), r;
   HIPCHK(hipMemcpyAsync(h.data(), G.wl[WL_PASS0 + slot], sizeof(int2) * n, hipMemcpyDeviceToHost, G.stream));
@@ -1935,8 +1940,11 @@ int make_fill_list(const Group& G, int slot, FillList& f) {
     for (int k = 0; k < f.reps; ++k)
       r.insert(r.end(), h.begin() + G.boff[slot][b], h.begin() + G.boff[slot][b] + G.bn[slot][b]);
   }
-  HIPCHK(hipMalloc(&f.d, sizeof(int2) * r.size()));
+  if (r.size() > 2 * (size_t)FILL_BLOCKS) return fail(FM_E_INVALID_ARG, "internal: repeated tile list too long");
+  f.d = region + (size_t)slot * 2 * FILL_BLOCKS;
   HIPCHK(hipMemcpyAsync(f.d, r.data(), sizeof(int2) * r.size(), hipMemcpyHostToDevice, G.stream));
+  // the host vector is released on return: the copy must have completed
+  HIPCHK(hipStreamSynchronize(G.stream));
   return 0;
 }
 
@@ -1977,12 +1985,11 @@ int profile_iterations(fm_plan* p, const fm_load_step* step, int32_t n_iter, dou
   std::vector<hipEvent_t> evs((size_t)n_iter * (FM_N_KERNELS + 1), nullptr);
   auto release = [&]() {
     (void)hipStreamSynchronize(st);
-    for (auto& f : fl)
-      if (f.d) { (void)hipFree(f.d); f.d = nullptr; }
     for (auto& x : evs)
       if (x) { (void)hipEventDestroy(x); x = nullptr; }
   };
-  for (int sl = 0; fill && sl < 5 && !rc; ++sl) rc = make_fill_list(G, sl, fl[sl]);
+  int2* region = (int2*)(p->ws + p->lay.fill);
+  for (int sl = 0; fill && sl < 5 && !rc; ++sl) rc = make_fill_list(G, sl, region, fl[sl]);
   for (size_t i = 0; i < evs.size() && !rc; ++i)
     if (hipEventCreate(&evs[i]) != hipSuccess) rc = fail(FM_E_HIP, "event create");
   if (rc) { release(); return rc; }
