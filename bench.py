@@ -287,8 +287,8 @@ def main():
                     help="also sweep the offered rate for the highest stable p99")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
-                                   "note only (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the solver runs on one GPU; sharding a solve or a batch "
+                                   "across GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
@@ -358,7 +358,8 @@ def main():
     tp_ms = sum(v["ms"] for v in passes.values())
     tp_bytes = sum(v["algorithmic_bytes"] for v in passes.values())
     if dom == "stress_div":
-        # the fused real-space step is bound by vector ALU issue
+        # the fused real-space step is bound by vector ALU issue (measured VALU busy
+        # fraction; its HBM traffic runs far below the copy ceiling)
         flops = sdiv_flops_per_voxel(prob) * Nv
         achieved = flops / (prof[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,

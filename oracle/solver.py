@@ -14,7 +14,7 @@ previous increment; then iterate (the loop of Algorithm 1):
   * Anderson acceleration on p
   * DTs of the accelerated p, Green operator, inverse DTs -> u^f
 
-Readings where the paper is silent or garbled (listed in the design doc):
+Readings where the paper is silent or garbled:
   * error  = h sqrt( sum_kept |D|^2 / sum_ip w_ip |sigma|_F^2 ), w_ip = 1/n_ppv
     (squared L2 norms; the printed ratio of norms is not dimensionless);
   * Anderson (Sec. 2.3 applies it every second or third iteration with a
