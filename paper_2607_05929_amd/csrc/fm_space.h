@@ -902,7 +902,11 @@ __device__ __forceinline__ void sdiv_tile_f32(const SolveDev* __restrict__ S, co
 // The FP64 variant of an FP32 group is launched every iteration but works
 // only for solves near their FP32 rounding floor: it runs as a few blocks
 // per compute unit walking the tile list, so that it costs a short dispatch
-// when no solve needs it.
+// when no solve needs it.  Block b owns the items b, b + G, b + 2G, ...
+// (G = gridDim.x); it checks 256 of them at once (one per thread: status
+// and flag of the item's solve) and then transforms only those that need
+// the FP64 step, so that a batch whose solves mostly run in FP32 costs one
+// round of flag loads per 256 items instead of one per item.
 // TR = 1 adds the applied-traction term D* at the loaded faces (groups whose
 // load paths carry tractions; the common kernel carries no traction code).
 template <typename R, int PL, typename CT = R, int TR = 0>
@@ -911,9 +915,25 @@ __global__ void __launch_bounds__(256, sizeof(CT) == 8 ? 1 : (sizeof(R) == 4 && 
   if constexpr (sizeof(R) == 4 && sizeof(CT) == 4 && PL == 0) {
     sdiv_tile_f32<R, TR>(S, work[blockIdx.x]);
   } else if constexpr (sizeof(R) == 4 && sizeof(CT) == 8) {
-    for (int i = blockIdx.x; i < nwork; i += gridDim.x) {
-      sdiv_tile<R, PL, CT, TR>(S, work[i]);
+    __shared__ int2 todo[256];
+    __shared__ int ntodo;
+    const int64_t G = gridDim.x;
+    for (int64_t i0 = blockIdx.x; i0 < nwork; i0 += G * 256) {
+      if (threadIdx.x == 0) ntodo = 0;
       __syncthreads();
+      const int64_t i = i0 + (int64_t)threadIdx.x * G;
+      if (i < nwork) {
+        const int2 w = work[i];
+        const FM_GLOBAL Ctrl* C = gconst(S[w.x].ctrl);
+        if (C->status == ST_RUNNING && C->rs64 != 0) todo[atomicAdd(&ntodo, 1)] = w;
+      }
+      __syncthreads();
+      const int nt = ntodo;
+      for (int k = 0; k < nt; ++k) {
+        sdiv_tile<R, PL, CT, TR>(S, todo[k]);
+        __syncthreads();
+      }
+      __syncthreads();   // every thread has read ntodo before the next reset
     }
   } else {
     sdiv_tile<R, PL, CT, TR>(S, work[blockIdx.x]);

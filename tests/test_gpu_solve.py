@@ -195,6 +195,24 @@ def test_autotuned_batch_matches_untuned(B):
     assert e < 1e-5
 
 
+def test_batch_fp64_finishing_equals_alone(B):
+    """Members of the batched family (32^3) that move their real-space step
+    to FP64 near the FP32 rounding floor, batched with members that do not:
+    the FP64 real-space kernel of the group (blocks scanning their tiles 256
+    at a time for solves that need it) gives every member exactly its own
+    solve's iterations and stress."""
+    probs = [p for p in W.config_batch(count=64) if p.n[0] == 32][:6]
+    alone = [B.solve(p, prec=W.FP32_MIXED, log_capacity=4000) for p in probs]
+    used = [any(e["rs_fp64"] for e in a["log"]) for a in alone]
+    print(f"fp64 finishing per member {used} iters {[a['iters'] for a in alone]}", flush=True)
+    assert any(used) and not all(used)
+    res = B.batch_solve(probs, prec=W.FP32_MIXED, fields=True)
+    for p, r, a in zip(probs, res, alone):
+        assert r["rc"] == 0
+        assert r["iters"] == a["iters"]
+        np.testing.assert_array_equal(r["sig"], a["sig"])
+
+
 def test_batch_long_pencils_equals_alone(B):
     """A batch whose solves put 512-point pencils on different axes: the
     persistent pipelined pass kernels take work items of several solves in
