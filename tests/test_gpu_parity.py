@@ -62,10 +62,12 @@ def test_green_apply(B, prec, seed, n, scheme, green):
 # the 512-point DFT shapes reach the E = 8 periodic (r2c and complex) kernels.
 # The 16-, 32-, 48- and 96-point pencils (n = 8, 16, 24, 48; DFT and the
 # doubled DTT lengths) take the kernels with two or four pencils per
-# wavefront (32 / 16 lanes each), also on the x passes with their wider tiles.
+# wavefront (32 / 16 lanes each), also on the x passes with their wider tiles;
+# the 96-cell y and z axes reach the FP32 kind-specific kernels of 96- and
+# 192-point pencils on complex (post-r2c) data.
 WAVE_SHAPES = [(256, 6, 5), (6, 256, 5), (5, 6, 256), (96, 160, 6), (192, 7, 128), (64, 32, 384),
                (512, 5, 6), (6, 512, 5), (5, 6, 512),
-               (48, 16, 5), (16, 48, 7), (5, 24, 48), (24, 7, 16), (8, 48, 24)]
+               (48, 16, 5), (16, 48, 7), (5, 24, 48), (24, 7, 16), (8, 48, 24), (6, 96, 5), (5, 6, 96)]
 BC_PATTERNS = {
     "P": [W.P, W.P], "N": [W.N, W.N], "D": [W.D, W.D], "ND": [W.N, W.D], "DN": [W.D, W.N],
 }
